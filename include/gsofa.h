@@ -1,0 +1,200 @@
+/*
+ * gsofa.h -- C ABI of the MI355X (gfx950) sparse symbolic LU factorisation
+ * library (method of Gaihre, Li, Liu, "gSoFa: Scalable Sparse Symbolic LU
+ * Factorization on GPUs", 2020).
+ *
+ * Problem (Introduction; Background, symbolic factorisation): given the
+ * nonzero pattern of a square sparse matrix A, already permuted for
+ * stability and fill reduction and stored as CSR, compute the nonzero
+ * structure of its LU factors (no pivoting, no numerical cancellation) and
+ * the supernode partition of the rows. By the fill-path theorem (Background)
+ * (i, j) is in L+U iff i == j or a directed path i -> ... -> j exists in the
+ * graph of A whose intermediate vertices are all smaller than both i and j.
+ * Graph model (Introduction): row i is vertex i; every stored off-diagonal
+ * (i, j) is an edge i -> j; diagonal entries add nothing.
+ *
+ * Conventions shared by every entry point:
+ *   - indices are int32, output offsets int64; 0-based.
+ *   - L is strictly lower (unit diagonal implied); U holds the diagonal
+ *     (always, even where A has no diagonal entry).
+ *   - default output layout: L as CSC (l_ptr[n+1], row indices ascending
+ *     within each column), U as CSR (u_ptr[n+1], column indices ascending).
+ *     GSOFA_L_CSR gives L as CSR (columns ascending within each row).
+ *   - supernodes follow Definition T3 (Background, supernodes): row s joins
+ *     the supernode running from r through s-1 iff
+ *     nnz(U(s,:)) == nnz(U(s-1,:)) - 1 and L(s, r) != 0. Detection runs on
+ *     independent blocks of max_supernode consecutive rows (the paper's
+ *     chunk size equals the maximum supernode size, Section 5), so no
+ *     supernode crosses a multiple of max_supernode and the first row of each
+ *     block starts one. xsup[k] is the first row of supernode k
+ *     (xsup[nsuper] = n); supno[i] is the supernode of row i.
+ *   - inputs are caller-owned and read-only; nothing is retained after a call
+ *     returns (serve_submit copies its input).
+ *   - results are library-owned; release them with gsofa_result_free.
+ *   - no C++ exception crosses this boundary; every entry point returns a
+ *     gsofa_status and leaves its output arguments untouched on error.
+ *   - one library instance drives the current HIP device of the calling
+ *     thread; calls from several threads on one device are serialised.
+ */
+#ifndef GSOFA_H
+#define GSOFA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define GSOFA_API __attribute__((visibility("default")))
+#else
+#define GSOFA_API
+#endif
+
+typedef enum {
+    GSOFA_OK = 0,
+    GSOFA_EINVAL = 1,     /* malformed input or argument                        */
+    GSOFA_ENOMEM = 2,     /* device budget below one source's working state      */
+    GSOFA_EDEVICE = 3,    /* a HIP runtime call failed                           */
+    GSOFA_EAGAIN = 4,     /* serve: request not finished yet                     */
+    GSOFA_ECAPACITY = 5,  /* serve: request larger than the admission budget     */
+    GSOFA_ENOTFOUND = 6   /* serve: unknown or already collected ticket          */
+} gsofa_status;
+
+/* option flags */
+#define GSOFA_NO_SUPERNODES     0x1u  /* skip supernode detection (nsuper = 0)        */
+#define GSOFA_L_CSR             0x2u  /* return L row-wise (skip the transpose)       */
+#define GSOFA_RESULT_ON_DEVICE  0x4u  /* result arrays stay in device memory          */
+#define GSOFA_INPUT_ON_DEVICE   0x8u  /* row_ptr / col_idx are device pointers        */
+#define GSOFA_NO_LINE95         0x10u /* ablation: relax labels of vertices already in
+                                         the structure (the paper's optional check,
+                                         Section 4, access-order paragraph, switched
+                                         off); results are unchanged                  */
+#define GSOFA_LEVEL_ORDER       0x20u /* ablation: the paper's breadth-first frontier
+                                         order instead of windowed order; results are
+                                         unchanged, work grows                        */
+
+/* A CSR pattern: n rows, row_ptr[n+1], col_idx[row_ptr[n]]; host pointers
+ * unless GSOFA_INPUT_ON_DEVICE is set. */
+typedef struct {
+    int32_t n;
+    const int32_t* row_ptr;
+    const int32_t* col_idx;
+} gsofa_csr;
+
+typedef struct {
+    int32_t status;             /* per-matrix status (batch, serve)                       */
+    int32_t iterations;         /* frontier-expansion steps, summed over sources          */
+    int32_t windows;            /* threshold windows, summed over sources                 */
+    int32_t concurrent_sources; /* sources in flight at once (#C)                         */
+    uint64_t edges_alg;         /* algorithmic edges: for each source row, deg(src) plus
+                                   deg(v) of every v < src reachable from src through
+                                   vertices < src (each counted once per source)          */
+    uint64_t edges_gpu;         /* edges actually scanned, revisits included              */
+    uint64_t peak_device_bytes; /* device working memory of this call                     */
+    double t_traverse_ms;       /* fill detection (seed + traversal)                      */
+    double t_emit_ms;           /* per-row sort, CSR assembly, L transpose                */
+    double t_supernode_ms;
+    double t_total_ms;          /* whole call, host copies included                       */
+} gsofa_stats;
+
+typedef void* (*gsofa_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*gsofa_free_fn)(void* ptr, void* ctx);
+
+typedef struct {
+    uint32_t struct_size;       /* sizeof(gsofa_opts); 0 or a zeroed struct = defaults   */
+    int32_t max_supernode;      /* block size for supernodes; 0 -> 128; <0 -> unbounded  */
+    int64_t mem_budget_bytes;   /* device working-memory cap; 0 -> 90 % of free memory    */
+    uint32_t flags;             /* GSOFA_* flags above                                    */
+    int32_t window;             /* threshold-window span (vertex ids); 0 -> autotuned    */
+    int32_t concurrent_sources; /* sources in flight; 0 -> planned from memory and CUs    */
+    void* stream;               /* hipStream_t to run on; NULL -> the null stream         */
+    gsofa_alloc_fn dev_alloc;   /* reserved for a caller-side device allocator; must be
+                                   NULL (GSOFA_EINVAL otherwise): device memory comes from
+                                   the library's cache, see gsofa_release_cache          */
+    gsofa_free_fn dev_free;     /* reserved; must be NULL                                 */
+    void* alloc_ctx;            /* reserved                                               */
+} gsofa_opts;
+
+typedef struct {
+    int32_t n;
+    int64_t nnz_a;              /* stored entries of A                                    */
+    int64_t nnz_l, nnz_u;       /* strict L; U with diagonal                              */
+    int64_t fills;              /* nnz(L) + nnz(U) - nnz(pattern(A) with diagonal)        */
+    int64_t* l_ptr;             /* [n+1]: CSC column pointers (CSR row pointers with
+                                   GSOFA_L_CSR)                                           */
+    int32_t* l_idx;             /* [nnz_l]                                                */
+    int64_t* u_ptr;             /* [n+1]: CSR row pointers of U                           */
+    int32_t* u_idx;             /* [nnz_u]                                                */
+    int32_t nsuper;
+    int32_t* xsup;              /* [nsuper+1]                                             */
+    int32_t* supno;             /* [n]                                                    */
+    uint32_t flags;             /* flags the result was produced with                     */
+    gsofa_stats stats;
+    void* internal_;            /* library bookkeeping; do not touch                      */
+} gsofa_result;
+
+typedef struct gsofa_server gsofa_server;
+
+/*
+ * Symbolic factorisation of one matrix: fill detection for every source row
+ * (Section 4: per-source traversal of the graph of A carrying, for every
+ * reached vertex, the smallest achievable maximum intermediate id, relaxed
+ * with atomic minimum, and the fill-path test), many sources concurrently
+ * (Section 4, multi-source paragraph), then supernodes (Section 5).
+ *   n >= 0; row_ptr[n+1] with row_ptr[0] == 0 and non-decreasing;
+ *   col_idx[row_ptr[n]] in [0, n), no repeated column within a row
+ *   (column order within a row is free; a missing diagonal is allowed).
+ * Errors: GSOFA_EINVAL for a malformed CSR or bad opts; GSOFA_ENOMEM when
+ * mem_budget_bytes cannot hold one source's state; GSOFA_EDEVICE on HIP
+ * failure. On success *out receives a new result.
+ */
+GSOFA_API int gsofa_symbolic(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                   const gsofa_opts* opts, gsofa_result** out);
+
+/*
+ * Many independent matrices in one pass: every (matrix, source row) pair is
+ * a work item of one persistent traversal launch; sorting, assembly and
+ * supernodes run once over the whole batch. outs[count] receives one result
+ * per matrix (each freed separately). Returns GSOFA_OK, or the first failing
+ * per-matrix status (every outs[i] is still set, with stats.status telling
+ * which ones failed and no arrays on those).
+ */
+GSOFA_API int gsofa_batch(int32_t count, const gsofa_csr* mats, const gsofa_opts* opts,
+                gsofa_result** outs);
+
+/*
+ * Request server with continuous batching: requests are admitted in arrival
+ * order while their estimated device memory fits the budget
+ * (opts->mem_budget_bytes) and fewer than max_inflight are running; admitted
+ * requests run concurrently on the device and finished ones release their
+ * memory, which admits the next.
+ *   serve_submit copies the CSR (host pointers) and returns a ticket.
+ *     GSOFA_ECAPACITY if the request alone can never fit the budget.
+ *   serve_poll waits up to timeout_us microseconds (0 = just test,
+ *     <0 = wait forever) for the ticket; GSOFA_EAGAIN if not done,
+ *     GSOFA_ENOTFOUND for an unknown or collected ticket; otherwise the
+ *     request's own status, with *out set on GSOFA_OK.
+ *   serve_close waits for running requests and frees the server.
+ */
+GSOFA_API int gsofa_serve_open(const gsofa_opts* opts, int32_t max_inflight, gsofa_server** srv);
+GSOFA_API int gsofa_serve_submit(gsofa_server* srv, const gsofa_csr* m, uint64_t* ticket);
+GSOFA_API int gsofa_serve_poll(gsofa_server* srv, uint64_t ticket, int32_t timeout_us,
+                     gsofa_result** out);
+GSOFA_API int gsofa_serve_close(gsofa_server* srv);
+
+/* Frees a result (host or device arrays). NULL is ignored. */
+GSOFA_API void gsofa_result_free(gsofa_result* r);
+
+/* Static text for a status code. */
+GSOFA_API const char* gsofa_strerror(int status);
+
+/* Releases cached device memory held between calls on the current device. */
+GSOFA_API int gsofa_release_cache(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSOFA_H */

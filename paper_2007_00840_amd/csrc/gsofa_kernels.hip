@@ -1,0 +1,955 @@
+// gfx950 kernels of the symbolic LU factorisation.
+//
+// Fill detection (Section 4 of the paper): for one source row s, every vertex
+// v < s reached from s carries a label, the smallest achievable maximum
+// intermediate vertex id over the paths s -> v found so far (the paper's
+// maxId). A frontier f passes max(label(f), f) to each neighbour w < s,
+// which keeps the atomic minimum; v joins L(s,:) when its label drops below v
+// (fill-path theorem, Background); any w > s adjacent to s or to a reached
+// vertex joins U(s,:). A vertex whose label improves while it is not yet in
+// the structure is expanded again (the paper's revisits).
+//
+// Schedule (our design; the paper expands breadth-first): a vertex already in
+// the structure always passes its own id on, so it is keyed by its id and
+// waits in a per-source pending bitmap; a vertex outside the structure is
+// keyed by its label. Keys never decrease along an edge, so the traversal runs
+// in windows of increasing keys: take the pending vertices with ids in
+// [lo, lo + window), relax breadth-first inside the window until no key in it
+// changes, then move on. A vertex finished in an earlier window can never
+// improve again, so it is marked settled in a bitmap that answers most edge
+// checks with one bit instead of a label. With window = n this is the paper's
+// breadth-first order.
+//
+// One wavefront owns one source slot at a time and pulls sources from a
+// global counter (largest ids first: their work grows with the id, Design
+// Challenges, challenge 2). Frontier compaction uses wavefront ballots and
+// lane prefix counts; per-slot state lives in HBM:
+//   lab   : label per vertex, value-range encoded per source so nothing is
+//           reset between sources (Section 4, maxId initialisation paragraph)
+//   V     : settled bitmap (in-structure vertices and finished windows)
+//   P     : pending bitmap of structure vertices waiting for their window
+//   qa/qb : current / next worklist, qs: per-level dedup stamps
+//   touch : reached vertices outside the structure (settled per window)
+//   rowb  : the source row's structure, copied to the output pool at the end
+#include "gsofa_internal.h"
+#include "gsofa.h"
+
+namespace gsofa {
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int t = __shfl_up(v, (unsigned)d, 64);
+        if (lane_id() >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int d = 32; d; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int d = 32; d; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_coherent(const T* p) {
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Order this wavefront's earlier global/LDS accesses before its later ones.
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Make this slot's plain stores visible and drop stale L1 lines.
+__device__ __forceinline__ void slot_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Append val for every lane with pred set; count is wave-uniform.
+__device__ __forceinline__ void wave_append(bool pred, int32_t val, int32_t* buf, int32_t& count) {
+    unsigned long long m = __ballot(pred);
+    if (pred) buf[count + (int32_t)lanes_below(m)] = val;
+    count += __popcll(m);
+}
+
+__global__ void k_zero_i32(int32_t* p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+SlotLayout slot_layout(int64_t N) {
+    SlotLayout L{};
+    if (N < 1) N = 1;
+    L.N = N;
+    L.nw32 = (N + 31) / 32;
+    L.nw64 = (N + 63) / 64;
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t r = o;
+        o += (bytes + 255) & ~int64_t(255);
+        return r;
+    };
+    L.off_lab = take(4 * N);
+    L.off_v = take(4 * L.nw32);
+    L.off_p = take(8 * L.nw64);
+    L.off_qs = take(4 * N);
+    L.off_meta = take(64);
+    L.off_qa = take(4 * N);
+    L.off_qb = take(4 * N);
+    L.off_touch = take(4 * N);
+    L.off_row = take(4 * N);
+    L.bytes_per_slot = o;
+    return L;
+}
+
+// ------------------------------------------------------------ slot init
+
+// lab = all ones, V = P = qs = meta = 0 (everything before off_qa).
+__global__ void k_init_slots(uint8_t* slots, int32_t nslots, SlotLayout lay) {
+    const int64_t words_lab = lay.N;
+    const int64_t words_rest = (lay.off_qa - lay.off_v) / 4;
+    for (int64_t sl = blockIdx.y; sl < nslots; sl += gridDim.y) {
+        uint32_t* base = (uint32_t*)(slots + sl * lay.bytes_per_slot);
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words_lab;
+             i += (int64_t)gridDim.x * blockDim.x)
+            base[i] = kInf;
+        uint32_t* rest = (uint32_t*)(slots + sl * lay.bytes_per_slot + lay.off_v);
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words_rest;
+             i += (int64_t)gridDim.x * blockDim.x)
+            rest[i] = 0u;
+    }
+}
+
+hipError_t launch_init_slots(uint8_t* slots, int32_t nslots, SlotLayout lay, hipStream_t st) {
+    if (nslots <= 0) return hipSuccess;
+    int64_t words = lay.N + (lay.off_qa - lay.off_v) / 4;
+    int gx = (int)std::min<int64_t>((words + 255) / 256, 64);
+    int gy = std::min(nslots, 4096);
+    hipLaunchKernelGGL(k_init_slots, dim3(gx, gy), dim3(256), 0, st, slots, nslots, lay);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ validation
+
+// Input checks for device-resident CSR: row_ptr[0] == 0, non-decreasing,
+// columns in [0, n). Rows whose bounds are broken are not read.
+__global__ void k_validate(const Job* jobs, int32_t njobs, int64_t max_n, int32_t* bad) {
+    const int32_t j = blockIdx.y;
+    if (j >= njobs) return;
+    const Job J = jobs[j];
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < J.n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        int32_t a = J.row_ptr[r], b = J.row_ptr[r + 1];
+        bool ok = (a >= 0) && (b >= a) && (r != 0 || a == 0);
+        if (ok) {
+            for (int32_t e = a; e < b; ++e) {
+                int32_t c = J.col_idx[e];
+                if (c < 0 || c >= J.n) { ok = false; break; }
+            }
+        }
+        if (!ok) atomicOr(&bad[j], 1);
+    }
+    (void)max_n;
+}
+
+hipError_t launch_validate(const Job* jobs_dev, int32_t njobs, int64_t max_n, int32_t* bad_dev,
+                           hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    int gx = (int)std::min<int64_t>((max_n + 255) / 256, 1024);
+    if (gx < 1) gx = 1;
+    hipLaunchKernelGGL(k_validate, dim3(gx, njobs), dim3(256), 0, st, jobs_dev, njobs, max_n, bad_dev);
+    return hipGetLastError();
+}
+
+__global__ void k_row_job(const Job* jobs, int32_t njobs, int32_t* row_job) {
+    const int32_t j = blockIdx.y;
+    if (j >= njobs) return;
+    const Job J = jobs[j];
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < J.n;
+         r += (int64_t)gridDim.x * blockDim.x)
+        row_job[J.row_base + r] = j;
+}
+
+hipError_t launch_row_job(const Job* jobs_dev, int32_t njobs, int64_t max_n, int32_t* row_job,
+                          hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    int gx = (int)std::min<int64_t>((max_n + 255) / 256, 1024);
+    if (gx < 1) gx = 1;
+    hipLaunchKernelGGL(k_row_job, dim3(gx, njobs), dim3(256), 0, st, jobs_dev, njobs, row_job);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------- traversal
+
+struct WaveTile {
+    int32_t scan[64];    // inclusive prefix of frontier degrees
+    int32_t start[64];   // first edge of each frontier
+    uint32_t outv[64];   // value each frontier passes on: max(label, id)
+};
+
+constexpr int kTravWaves = 4;
+
+__global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
+    __shared__ WaveTile tiles[kTravWaves];
+    const int wv = threadIdx.x >> 6;
+    const int ln = lane_id();
+    const int32_t slot = blockIdx.x * kTravWaves + wv;
+    if (slot >= a.nslots) return;
+    WaveTile& T = tiles[wv];
+
+    uint8_t* sb = a.slots + (int64_t)slot * a.lay.bytes_per_slot;
+    uint32_t* lab = (uint32_t*)(sb + a.lay.off_lab);
+    uint32_t* V = (uint32_t*)(sb + a.lay.off_v);
+    unsigned long long* P = (unsigned long long*)(sb + a.lay.off_p);
+    int32_t* qa = (int32_t*)(sb + a.lay.off_qa);
+    int32_t* qb = (int32_t*)(sb + a.lay.off_qb);
+    uint32_t* qs = (uint32_t*)(sb + a.lay.off_qs);
+    int32_t* touch = (int32_t*)(sb + a.lay.off_touch);
+    int32_t* rowb = (int32_t*)(sb + a.lay.off_row);
+    uint32_t* meta = (uint32_t*)(sb + a.lay.off_meta);
+
+    const uint32_t R = (uint32_t)a.lay.N;
+    const uint32_t emax = 0xFFFFFFFFu / R;
+    uint32_t epoch = meta[0];
+    uint32_t lvl = meta[1];
+    const bool line95 = (a.flags & GSOFA_NO_LINE95) == 0;
+    const int32_t D = a.window > 0 ? a.window : 1;
+
+    for (;;) {
+        unsigned long long k = 0;
+        if (ln == 0) k = atomicAdd(a.item_counter, 1ull);
+        k = __shfl(k, 0, 64);
+        if (k >= (unsigned long long)a.nitems) break;
+
+        int32_t j, s;
+        if (a.item_rows) {
+            const int64_t gr = a.item_rows[k];
+            j = a.row_job ? a.row_job[gr] : 0;
+            s = (int32_t)(gr - a.jobs[j].row_base);
+        } else {
+            int32_t lo = 0, hi = a.njobs - 1;
+            while (lo < hi) {
+                int32_t mid = (lo + hi + 1) >> 1;
+                if (a.jobs[mid].item_base <= (int64_t)k) lo = mid;
+                else hi = mid - 1;
+            }
+            j = lo;
+            s = a.jobs[j].n - 1 - (int32_t)((int64_t)k - a.jobs[j].item_base);
+        }
+        j = __builtin_amdgcn_readfirstlane(j);
+        s = __builtin_amdgcn_readfirstlane(s);
+        const int32_t* rp = a.jobs[j].row_ptr;
+        const int32_t* ci = a.jobs[j].col_idx;
+        const int64_t grow = a.jobs[j].row_base + s;
+
+        // fresh label range for this source (reset once the 32-bit range is used up)
+        if (epoch >= emax) {
+            for (int64_t i = ln; i < (int64_t)R; i += 64) lab[i] = kInf;
+            epoch = 0;
+            slot_fence();
+        }
+        if (lvl >= 0xF0000000u) {
+            for (int64_t i = ln; i < (int64_t)R; i += 64) qs[i] = 0u;
+            lvl = 0;
+            slot_fence();
+        }
+        ++epoch;
+        const uint32_t base = 0xFFFFFFFFu - epoch * R;
+        auto dec = [&](uint32_t v) -> uint32_t {
+            return (v >= base && v - base < R) ? v - base : kInf;
+        };
+
+        unsigned long long e_alg = 0, e_gpu = 0;
+        int32_t rcount = 0, lcount = 0, tcount = 0;
+        uint32_t n_iter = 0, n_win = 0;
+
+        // ---- seed: the source row's own entries (original entries of row s)
+        const int32_t rs = rp[s], re = rp[s + 1];
+        int32_t ndiag = 0;
+        bool dup = false;
+        int32_t pmin = 0x7FFFFFFF;
+        for (int32_t e0 = rs; e0 < re; e0 += 64) {
+            const int32_t e = e0 + ln;
+            const bool act = e < re;
+            const int32_t w = act ? ci[e] : -1;
+            ndiag += __popcll(__ballot(act && w == s));
+            bool fresh = false;
+            if (act && w != s) {
+                const uint32_t bit = 1u << (w & 31);
+                const uint32_t old = atomicOr(&V[w >> 5], bit);
+                fresh = (old & bit) == 0;
+                dup |= !fresh;
+            }
+            const bool below = fresh && w < s;
+            wave_append(fresh, w, rowb, rcount);
+            lcount += __popcll(__ballot(below));
+            if (below) {
+                lab[w] = base;  // label 0: no intermediate vertex
+                atomicOr(&P[w >> 6], 1ull << (w & 63));
+                e_alg += (unsigned long long)(rp[w + 1] - rp[w]);
+                pmin = min(pmin, w);
+            }
+        }
+        if (ln == 0) {
+            e_alg += (unsigned long long)(re - rs);
+            e_gpu += (unsigned long long)(re - rs);
+        }
+        if (__ballot(dup) != 0ull || ndiag > 1) {
+            if (ln == 0) atomicOr(&a.jstats[j].err, kErrDuplicate);
+        }
+        pmin = wave_min(pmin);
+        slot_fence();
+
+        // ---- windows of increasing keys
+        const int32_t nwp = (s + 63) >> 6;  // pending words covering [0, s)
+        int32_t pos = pmin;
+        while (pos < s) {
+            // lowest pending vertex >= pos
+            int32_t found = -1;
+            for (int32_t w0 = pos >> 6; w0 < nwp; w0 += 64) {
+                const int32_t wi = w0 + ln;
+                const unsigned long long word = (wi < nwp) ? ld_coherent(&P[wi]) : 0ull;
+                const unsigned long long nz = __ballot(word != 0ull);
+                if (nz) {
+                    const int jl = __builtin_ctzll(nz);
+                    const unsigned long long wd = __shfl(word, jl, 64);
+                    found = (w0 + jl) * 64 + __builtin_ctzll(wd);
+                    break;
+                }
+            }
+            if (found < 0) break;
+            const int32_t lo = found;
+            const int32_t hi = (int32_t)min((int64_t)lo + D, (int64_t)s);
+            ++n_win;
+
+            // extract the pending vertices of [lo, hi) into the worklist
+            int32_t* cur = qa;
+            int32_t* nxt = qb;
+            int32_t qn = 0;
+            const int32_t wlast = (hi - 1) >> 6;
+            for (int32_t w0 = lo >> 6; w0 <= wlast; w0 += 64) {
+                const int32_t wi = w0 + ln;
+                unsigned long long word = 0ull;
+                if (wi <= wlast) {
+                    word = ld_coherent(&P[wi]);
+                    const int64_t b0 = (int64_t)wi * 64;
+                    unsigned long long m = ~0ull;
+                    if (b0 < lo) m &= ~0ull << (lo - b0);
+                    if (b0 + 64 > hi) m &= (hi - b0 >= 64) ? ~0ull : ((1ull << (hi - b0)) - 1ull);
+                    word &= m;
+                    if (word) atomicAnd(&P[wi], ~word);
+                }
+                const int c = __popcll(word);
+                const int incl = wave_incl_scan(c);
+                int32_t o = qn + incl - c;
+                while (word) {
+                    const int b = __builtin_ctzll(word);
+                    word &= word - 1ull;
+                    cur[o++] = wi * 64 + b;
+                }
+                qn += __shfl(incl, 63, 64);
+            }
+            const int32_t tmark = tcount;
+            wave_fence();
+
+            // breadth-first label correction inside the window
+            while (qn > 0) {
+                ++lvl;
+                ++n_iter;
+                int32_t nq = 0;
+                for (int32_t c0 = 0; c0 < qn; c0 += 64) {
+                    const int32_t i = c0 + ln;
+                    const bool act = i < qn;
+                    int32_t fs = 0, deg = 0;
+                    uint32_t ov = kInf;
+                    if (act) {
+                        const int32_t f = ld_coherent(&cur[i]);
+                        fs = rp[f];
+                        deg = rp[f + 1] - fs;
+                        const uint32_t dl = dec(ld_coherent(&lab[f]));
+                        ov = (dl == kInf) ? kInf : max(dl, (uint32_t)f);
+                    }
+                    e_gpu += (unsigned long long)deg;
+                    const int32_t incl = wave_incl_scan(deg);
+                    const int32_t total = __shfl(incl, 63, 64);
+                    T.scan[ln] = incl;
+                    T.start[ln] = fs;
+                    T.outv[ln] = ov;
+                    wave_fence();
+                    for (int32_t r0 = 0; r0 < total; r0 += 64) {
+                        const int32_t ei = r0 + ln;
+                        const bool eact = ei < total;
+                        int32_t jl = 0, jh = 63;
+                        while (jl < jh) {
+                            const int32_t mid = (jl + jh) >> 1;
+                            if (T.scan[mid] > ei) jh = mid;
+                            else jl = mid + 1;
+                        }
+                        const int32_t excl = jl ? T.scan[jl - 1] : 0;
+                        const int32_t w = eact ? ci[T.start[jl] + (ei - excl)] : s;
+                        const uint32_t outv = T.outv[jl];
+
+                        bool emit = false, isl = false, push = false, touched = false;
+                        if (w != s) {
+                            const uint32_t bit = 1u << (w & 31);
+                            bool settled = false;
+                            if (w > s || line95) settled = (V[w >> 5] & bit) != 0u;
+                            if (!settled) {
+                                if (w > s) {
+                                    const uint32_t old = atomicOr(&V[w >> 5], bit);
+                                    emit = (old & bit) == 0u;
+                                } else if (outv < dec(lab[w])) {
+                                    const uint32_t old = atomicMin(&lab[w], base + outv);
+                                    const uint32_t dold = dec(old);
+                                    if (outv < dold) {
+                                        if (dold == kInf)
+                                            e_alg += (unsigned long long)(rp[w + 1] - rp[w]);
+                                        if (dold >= (uint32_t)w) {
+                                            if (outv < (uint32_t)w) {
+                                                // label fell below w: fill (s, w)
+                                                emit = true;
+                                                isl = true;
+                                                atomicOr(&V[w >> 5], bit);
+                                                if (w < hi) push = true;
+                                                else atomicOr(&P[w >> 6], 1ull << (w & 63));
+                                            } else {
+                                                push = true;
+                                                touched = (dold == kInf);
+                                            }
+                                        }
+                                    }
+                                }
+                            }
+                        }
+                        if (push) push = atomicExch(&qs[w], lvl) != lvl;
+                        wave_append(emit, w, rowb, rcount);
+                        lcount += __popcll(__ballot(isl));
+                        wave_append(push, w, nxt, nq);
+                        wave_append(touched, w, touch, tcount);
+                    }
+                    wave_fence();
+                }
+                int32_t* t = cur;
+                cur = nxt;
+                nxt = t;
+                qn = nq;
+                wave_fence();
+            }
+            // everything reached in this window is final now
+            for (int32_t i = tmark + ln; i < tcount; i += 64) {
+                const int32_t v = ld_coherent(&touch[i]);
+                atomicOr(&V[v >> 5], 1u << (v & 31));
+            }
+            pos = hi;
+        }
+
+        // ---- finish the row: diagonal, copy to the pool, clear the bitmaps
+        if (ln == 0) rowb[rcount] = s;
+        rcount += 1;
+        slot_fence();
+        unsigned long long off = 0;
+        if (ln == 0) off = atomicAdd(a.pool_tail, (unsigned long long)rcount);
+        off = __shfl(off, 0, 64);
+        const bool fits = (int64_t)(off + rcount) <= a.pool_cap;
+        if (fits)
+            for (int32_t i = ln; i < rcount; i += 64) a.pool[off + i] = ld_coherent(&rowb[i]);
+        if (ln == 0) {
+            a.row_off[grow] = fits ? (int64_t)off : -1;
+            a.row_cnt[grow] = rcount;
+            a.row_lcnt[grow] = lcount;
+            if (!fits) atomicOr(&a.jstats[j].err, kErrOverflow);
+        }
+        for (int32_t i = ln; i < rcount; i += 64) V[ld_coherent(&rowb[i]) >> 5] = 0u;
+        for (int32_t i = ln; i < tcount; i += 64) V[ld_coherent(&touch[i]) >> 5] = 0u;
+
+        e_alg = wave_sum_u64(e_alg);
+        e_gpu = wave_sum_u64(e_gpu);
+        if (ln == 0) {
+            atomicAdd(&a.jstats[j].edges_alg, e_alg);
+            atomicAdd(&a.jstats[j].edges_gpu, e_gpu);
+            atomicAdd(&a.jstats[j].iterations, (unsigned long long)n_iter);
+            atomicAdd(&a.jstats[j].windows, (unsigned long long)n_win);
+            if (ndiag > 0) atomicAdd(&a.jstats[j].diag, 1ull);
+        }
+        slot_fence();
+    }
+    if (ln == 0) {
+        meta[0] = epoch;
+        meta[1] = lvl;
+    }
+}
+
+hipError_t launch_traverse(const TraverseArgs& a, hipStream_t st) {
+    if (a.nslots <= 0 || a.nitems <= 0) return hipSuccess;
+    const int blocks = (a.nslots + kTravWaves - 1) / kTravWaves;
+    hipLaunchKernelGGL(k_traverse, dim3(blocks), dim3(64 * kTravWaves), 0, st, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ scan
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+int64_t scan_scratch_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+__device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t* sh, int64_t& total) {
+    // sh: kScanThreads/64 entries
+    const int ln = lane_id(), wv = threadIdx.x >> 6;
+    int64_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t t = __shfl_up(x, (unsigned)d, 64);
+        if (ln >= d) x += t;
+    }
+    if (ln == 63) sh[wv] = x;
+    __syncthreads();
+    int64_t pre = 0, tot = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        if (w < wv) pre += sh[w];
+        tot += sh[w];
+    }
+    __syncthreads();
+    total = tot;
+    return pre + x - v;
+}
+
+__device__ __forceinline__ int64_t scan_val(const int32_t* a, const int32_t* b, int64_t i, int64_t n) {
+    if (i >= n) return 0;
+    return (int64_t)a[i] - (b ? (int64_t)b[i] : 0);
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* a, const int32_t* b,
+                                                              int64_t n, int64_t* partial) {
+    __shared__ int64_t sh[kScanThreads / 64];
+    const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+    int64_t sum = 0;
+    for (int k = 0; k < kScanItems; ++k) sum += scan_val(a, b, t0 + (int64_t)k * kScanThreads + threadIdx.x, n);
+    int64_t total;
+    block_excl_scan(sum, sh, total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(int64_t* partial, int64_t nb) {
+    __shared__ int64_t sh[kScanThreads / 64];
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < nb; c0 += kScanThreads) {
+        const int64_t i = c0 + threadIdx.x;
+        const int64_t v = i < nb ? partial[i] : 0;
+        int64_t total;
+        const int64_t ex = block_excl_scan(v, sh, total);
+        if (i < nb) partial[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) partial[nb] = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* a, const int32_t* b, int64_t n,
+                                                             int64_t nb, const int64_t* partial, int64_t* out) {
+    __shared__ int64_t sh[kScanThreads / 64];
+    const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+    // each thread owns kScanItems consecutive elements
+    int64_t v[kScanItems];
+    int64_t sum = 0;
+    const int64_t my0 = t0 + (int64_t)threadIdx.x * kScanItems;
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = scan_val(a, b, my0 + k, n);
+        sum += v[k];
+    }
+    int64_t total;
+    int64_t run = (blockIdx.x < nb ? partial[blockIdx.x] : 0) + block_excl_scan(sum, sh, total);
+    for (int k = 0; k < kScanItems; ++k) {
+        if (my0 + k < n) out[my0 + k] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = partial[nb];
+}
+
+hipError_t launch_scan_counts(const int32_t* a, const int32_t* b, int64_t n, int64_t* out,
+                              int64_t* scratch, hipStream_t st) {
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 0) {
+        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, scratch, (int64_t)0);
+        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanThreads), 0, st, a, b, (int64_t)0, (int64_t)0,
+                           scratch, out);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, a, b, n, scratch);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, scratch, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, st, a, b, n, nb, scratch, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- segment sorting
+//
+// A segment holds distinct int32 values. Sorted ascending, its first `split`
+// values go to outA and the rest to outB.
+
+constexpr int kSmallSeg = 256;     // one wavefront, LDS bitonic
+constexpr int kBigSeg = 16384;     // one block, LDS bitonic
+constexpr int kBitmapBits = 1 << 19;  // 64 KB LDS bitmap per pass
+
+__device__ __forceinline__ void write_split(int32_t idx, int32_t v, int32_t split, int32_t* outA,
+                                            int32_t* outB) {
+    if (idx < split) outA[idx] = v;
+    else outB[idx - split] = v;
+}
+
+// wavefront bitonic sort of up to 256 values in LDS buffer buf[256]
+__device__ void wave_sort_segment(const int32_t* in, int32_t cnt, int32_t split, int32_t* outA,
+                                  int32_t* outB, int32_t* buf) {
+    const int ln = lane_id();
+    int32_t m = 1;
+    while (m < cnt) m <<= 1;
+    for (int i = ln; i < m; i += 64) buf[i] = i < cnt ? in[i] : 0x7FFFFFFF;
+    wave_fence();
+    for (int32_t k = 2; k <= m; k <<= 1) {
+        for (int32_t jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int32_t i = ln; i < m; i += 64) {
+                const int32_t ixj = i ^ jj;
+                if (ixj > i) {
+                    const int32_t x = buf[i], y = buf[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        buf[i] = y;
+                        buf[ixj] = x;
+                    }
+                }
+            }
+            wave_fence();
+        }
+    }
+    for (int i = ln; i < cnt; i += 64) write_split(i, buf[i], split, outA, outB);
+    wave_fence();
+}
+
+// block bitonic sort of up to kBigSeg values; falls back to bitmap ranking
+// for longer segments (values distinct and >= 0).
+__device__ void block_sort_segment(const int32_t* in, int32_t cnt, int32_t split, int32_t* outA,
+                                   int32_t* outB, int32_t* buf /* kBigSeg ints = 64 KB */) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (cnt <= kBigSeg) {
+        int32_t m = 1;
+        while (m < cnt) m <<= 1;
+        for (int i = tid; i < m; i += nt) buf[i] = i < cnt ? in[i] : 0x7FFFFFFF;
+        __syncthreads();
+        for (int32_t k = 2; k <= m; k <<= 1) {
+            for (int32_t jj = k >> 1; jj > 0; jj >>= 1) {
+                for (int32_t i = tid; i < m; i += nt) {
+                    const int32_t ixj = i ^ jj;
+                    if (ixj > i) {
+                        const int32_t x = buf[i], y = buf[ixj];
+                        const bool up = (i & k) == 0;
+                        if ((x > y) == up) {
+                            buf[i] = y;
+                            buf[ixj] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = tid; i < cnt; i += nt) write_split(i, buf[i], split, outA, outB);
+        __syncthreads();
+        return;
+    }
+    // bitmap ranking over value chunks of kBitmapBits
+    __shared__ int32_t red[2];
+    __shared__ int32_t wsum[16];
+    uint32_t* bm = (uint32_t*)buf;
+    int32_t vmin = 0x7FFFFFFF, vmax = -1;
+    for (int i = tid; i < cnt; i += nt) {
+        const int32_t v = in[i];
+        vmin = min(vmin, v);
+        vmax = max(vmax, v);
+    }
+    if (tid == 0) { red[0] = 0x7FFFFFFF; red[1] = -1; }
+    __syncthreads();
+    atomicMin(&red[0], vmin);
+    atomicMax(&red[1], vmax);
+    __syncthreads();
+    vmin = red[0];
+    vmax = red[1];
+    int32_t rank_base = 0;
+    const int nwords = kBitmapBits / 32;
+    const int per_t = nwords / nt;  // words per thread (nt divides nwords)
+    for (int64_t c0 = vmin; c0 <= vmax; c0 += kBitmapBits) {
+        for (int i = tid; i < nwords; i += nt) bm[i] = 0u;
+        __syncthreads();
+        for (int i = tid; i < cnt; i += nt) {
+            const int64_t d = (int64_t)in[i] - c0;
+            if (d >= 0 && d < kBitmapBits) atomicOr(&bm[d >> 5], 1u << (d & 31));
+        }
+        __syncthreads();
+        // each thread owns per_t consecutive words: count, block scan, emit
+        int32_t mine = 0;
+        for (int q = 0; q < per_t; ++q) mine += __popc(bm[tid * per_t + q]);
+        int32_t x = mine;
+        for (int d = 1; d < 64; d <<= 1) {
+            int32_t t = __shfl_up(x, (unsigned)d, 64);
+            if (lane_id() >= d) x += t;
+        }
+        if (lane_id() == 63) wsum[tid >> 6] = x;
+        __syncthreads();
+        int32_t pre = 0, tot = 0;
+        for (int w = 0; w < nt / 64; ++w) {
+            if (w < (tid >> 6)) pre += wsum[w];
+            tot += wsum[w];
+        }
+        int32_t r = rank_base + pre + x - mine;
+        for (int q = 0; q < per_t; ++q) {
+            uint32_t word = bm[tid * per_t + q];
+            while (word) {
+                const int b = __builtin_ctz(word);
+                word &= word - 1u;
+                const int32_t v = (int32_t)(c0 + (int64_t)(tid * per_t + q) * 32 + b);
+                write_split(r++, v, split, outA, outB);
+            }
+        }
+        rank_base += tot;
+        __syncthreads();
+    }
+}
+
+// rows: pool segment -> L (entries < row) and U (entries >= row)
+__global__ __launch_bounds__(256) void k_sort_rows_small(int64_t nrows, const int64_t* row_off,
+                                                         const int32_t* row_cnt, const int32_t* row_lcnt,
+                                                         const int32_t* pool, const int64_t* u_ptr,
+                                                         int32_t* u_idx, const int64_t* l_ptr,
+                                                         int32_t* l_idx, int32_t* big_list,
+                                                         int32_t* big_count) {
+    __shared__ int32_t buf[4][kSmallSeg];
+    const int wv = threadIdx.x >> 6;
+    const int64_t r = (int64_t)blockIdx.x * 4 + wv;
+    if (r >= nrows) return;
+    const int32_t cnt = row_cnt[r];
+    if (cnt > kSmallSeg) {
+        if (lane_id() == 0) big_list[atomicAdd(big_count, 1)] = (int32_t)r;
+        return;
+    }
+    wave_sort_segment(pool + row_off[r], cnt, row_lcnt[r], l_idx + l_ptr[r], u_idx + u_ptr[r], buf[wv]);
+}
+
+__global__ __launch_bounds__(256) void k_sort_rows_big(const int64_t* row_off, const int32_t* row_cnt,
+                                                       const int32_t* row_lcnt, const int32_t* pool,
+                                                       const int64_t* u_ptr, int32_t* u_idx,
+                                                       const int64_t* l_ptr, int32_t* l_idx,
+                                                       const int32_t* big_list, const int32_t* big_count) {
+    __shared__ int32_t buf[kBigSeg];
+    const int32_t nb = *big_count;
+    for (int32_t q = blockIdx.x; q < nb; q += gridDim.x) {
+        const int32_t r = big_list[q];
+        block_sort_segment(pool + row_off[r], row_cnt[r], row_lcnt[r], l_idx + l_ptr[r],
+                           u_idx + u_ptr[r], buf);
+    }
+}
+
+hipError_t launch_sort_rows(RowSpace rs, const int64_t* row_off, const int32_t* row_cnt,
+                            const int32_t* row_lcnt, const int32_t* pool, const int64_t* u_ptr,
+                            int32_t* u_idx, const int64_t* l_ptr, int32_t* l_idx, int32_t* big_list,
+                            int32_t* big_count, hipStream_t st) {
+    if (rs.nrows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, big_count, (int64_t)1);
+    hipLaunchKernelGGL(k_sort_rows_small, dim3((unsigned)((rs.nrows + 3) / 4)), dim3(256), 0, st,
+                       rs.nrows, row_off, row_cnt, row_lcnt, pool, u_ptr, u_idx, l_ptr, l_idx,
+                       big_list, big_count);
+    hipLaunchKernelGGL(k_sort_rows_big, dim3(1024), dim3(256), 0, st, row_off, row_cnt, row_lcnt, pool,
+                       u_ptr, u_idx, l_ptr, l_idx, big_list, big_count);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ L transpose
+
+__device__ __forceinline__ int64_t job_base_of(const RowSpace& rs, int64_t r) {
+    return rs.row_job ? rs.job_row_base[rs.row_job[r]] : 0;
+}
+
+// column counts of L (global column = job base + local column)
+__global__ __launch_bounds__(256) void k_col_hist(RowSpace rs, const int64_t* l_rptr,
+                                                  const int32_t* l_ridx, int32_t* col_cnt) {
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rs.nrows) return;
+    const int64_t b = job_base_of(rs, r);
+    for (int64_t e = l_rptr[r] + lane_id(); e < l_rptr[r + 1]; e += 64) atomicAdd(&col_cnt[b + l_ridx[e]], 1);
+}
+
+__global__ __launch_bounds__(256) void k_col_scatter(RowSpace rs, const int64_t* l_rptr,
+                                                     const int32_t* l_ridx, const int64_t* l_cptr,
+                                                     int32_t* cursor, int32_t* tmp) {
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rs.nrows) return;
+    const int64_t b = job_base_of(rs, r);
+    const int32_t local = (int32_t)(r - b);
+    for (int64_t e = l_rptr[r] + lane_id(); e < l_rptr[r + 1]; e += 64) {
+        const int64_t c = b + l_ridx[e];
+        tmp[l_cptr[c] + atomicAdd(&cursor[c], 1)] = local;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sort_cols_small(int64_t ncols, const int64_t* cptr,
+                                                         const int32_t* tmp, int32_t* out,
+                                                         int32_t* big_list, int32_t* big_count) {
+    __shared__ int32_t buf[4][kSmallSeg];
+    const int wv = threadIdx.x >> 6;
+    const int64_t c = (int64_t)blockIdx.x * 4 + wv;
+    if (c >= ncols) return;
+    const int32_t cnt = (int32_t)(cptr[c + 1] - cptr[c]);
+    if (cnt > kSmallSeg) {
+        if (lane_id() == 0) big_list[atomicAdd(big_count, 1)] = (int32_t)c;
+        return;
+    }
+    wave_sort_segment(tmp + cptr[c], cnt, cnt, out + cptr[c], nullptr, buf[wv]);
+}
+
+__global__ __launch_bounds__(256) void k_sort_cols_big(const int64_t* cptr, const int32_t* tmp,
+                                                       int32_t* out, const int32_t* big_list,
+                                                       const int32_t* big_count) {
+    __shared__ int32_t buf[kBigSeg];
+    const int32_t nb = *big_count;
+    for (int32_t q = blockIdx.x; q < nb; q += gridDim.x) {
+        const int32_t c = big_list[q];
+        const int32_t cnt = (int32_t)(cptr[c + 1] - cptr[c]);
+        block_sort_segment(tmp + cptr[c], cnt, cnt, out + cptr[c], nullptr, buf);
+    }
+}
+
+hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_zero_i32, dim3(g), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_l(RowSpace rs, const int64_t* l_rptr, const int32_t* l_ridx,
+                              int32_t* col_cnt, int64_t* l_cptr, int32_t* l_cidx,
+                              int64_t* scan_scratch, int32_t* cursor, int32_t* tmp,
+                              int32_t* big_list, int32_t* big_count, hipStream_t st) {
+    const int64_t n = rs.nrows;
+    if (n <= 0) return launch_scan_counts(col_cnt, nullptr, 0, l_cptr, scan_scratch, st);
+    const unsigned zb = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_zero_i32, dim3(zb), dim3(256), 0, st, col_cnt, n);
+    hipLaunchKernelGGL(k_zero_i32, dim3(zb), dim3(256), 0, st, cursor, n);
+    const unsigned rb = (unsigned)((n + 3) / 4);
+    hipLaunchKernelGGL(k_col_hist, dim3(rb), dim3(256), 0, st, rs, l_rptr, l_ridx, col_cnt);
+    hipError_t e = launch_scan_counts(col_cnt, nullptr, n, l_cptr, scan_scratch, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_col_scatter, dim3(rb), dim3(256), 0, st, rs, l_rptr, l_ridx, l_cptr, cursor, tmp);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, big_count, (int64_t)1);
+    hipLaunchKernelGGL(k_sort_cols_small, dim3(rb), dim3(256), 0, st, n, l_cptr, tmp, l_cidx, big_list, big_count);
+    hipLaunchKernelGGL(k_sort_cols_big, dim3(1024), dim3(256), 0, st, l_cptr, tmp, l_cidx, big_list, big_count);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------- supernodes
+//
+// Definition T3 inside independent blocks of rows (Section 5). Phase I: a row
+// s > block start with nnz(U(s,:)) == nnz(U(s-1,:)) - 1 may extend the
+// supernode above it; every other row leads one. Phase II: each leader walks
+// the rows after it while phase I allows, checking L(s, r) != 0 for the
+// current supernode start r; where it fails, s starts a new supernode.
+
+__device__ __forceinline__ int64_t ucount(const int64_t* u_ptr, int64_t r) { return u_ptr[r + 1] - u_ptr[r]; }
+
+__device__ __forceinline__ bool l_has(const int64_t* l_rptr, const int32_t* l_ridx, int64_t s, int32_t col) {
+    int64_t lo = l_rptr[s], hi = l_rptr[s + 1];
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (l_ridx[mid] < col) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < l_rptr[s + 1] && l_ridx[lo] == col;
+}
+
+__global__ __launch_bounds__(256) void k_supernodes(RowSpace rs, int64_t nblocks, const int64_t* first,
+                                                    const int32_t* len, const int64_t* u_ptr,
+                                                    const int64_t* l_rptr, const int32_t* l_ridx,
+                                                    int32_t* is_start) {
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= nblocks) return;
+    const int64_t f0 = first[b];
+    const int64_t end = f0 + len[b];
+    const int64_t jb = job_base_of(rs, f0);
+    for (int64_t s = f0 + lane_id(); s < end; s += 64) {
+        const bool follower = s > f0 && ucount(u_ptr, s) == ucount(u_ptr, s - 1) - 1;
+        is_start[s] = follower ? 0 : 1;
+    }
+    wave_fence();
+    for (int64_t r0 = f0 + lane_id(); r0 < end; r0 += 64) {
+        const bool leader = !(r0 > f0 && ucount(u_ptr, r0) == ucount(u_ptr, r0 - 1) - 1);
+        if (!leader) continue;
+        int64_t r = r0;
+        for (int64_t s = r0 + 1; s < end; ++s) {
+            if (ucount(u_ptr, s) != ucount(u_ptr, s - 1) - 1) break;  // next phase-I leader
+            if (!l_has(l_rptr, l_ridx, s, (int32_t)(r - jb))) {
+                is_start[s] = 1;
+                r = s;
+            }
+        }
+    }
+}
+
+hipError_t launch_supernodes(RowSpace rs, int64_t nblocks, const int64_t* block_first_row,
+                             const int32_t* block_len, const int64_t* u_ptr, const int64_t* l_rptr,
+                             const int32_t* l_ridx, int32_t* is_start, hipStream_t st) {
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_supernodes, dim3((unsigned)((nblocks + 3) / 4)), dim3(256), 0, st, rs, nblocks,
+                       block_first_row, block_len, u_ptr, l_rptr, l_ridx, is_start);
+    return hipGetLastError();
+}
+
+__global__ void k_sn_assemble(RowSpace rs, const int32_t* is_start, const int64_t* scan, int32_t* xsup,
+                              int32_t* supno) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rs.nrows;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = rs.row_job ? rs.row_job[r] : 0;
+        const int64_t b = rs.row_job ? rs.job_row_base[j] : 0;
+        const int64_t k = scan[r];  // supernode starts before r, all jobs
+        if (is_start[r]) xsup[k + j] = (int32_t)(r - b);
+        supno[r] = (int32_t)(k + is_start[r] - 1 - scan[b]);
+    }
+}
+
+__global__ void k_sn_terminal(int32_t njobs, const int64_t* job_row_base, const int32_t* job_n,
+                              const int64_t* scan, int32_t* xsup) {
+    for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < njobs; j += gridDim.x * blockDim.x)
+        xsup[scan[job_row_base[j] + job_n[j]] + j] = job_n[j];
+}
+
+hipError_t launch_supernode_assemble(RowSpace rs, int32_t njobs, const int32_t* is_start,
+                                     const int64_t* start_scan, int32_t* xsup_all, int32_t* supno_all,
+                                     hipStream_t st) {
+    (void)njobs;
+    if (rs.nrows <= 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<int64_t>((rs.nrows + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_sn_assemble, dim3(g), dim3(256), 0, st, rs, is_start, start_scan, xsup_all, supno_all);
+    return hipGetLastError();
+}
+
+hipError_t launch_supernode_terminals(int32_t njobs, const int64_t* job_row_base, const int32_t* job_n,
+                                      const int64_t* start_scan, int32_t* xsup_all, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<int64_t>((njobs + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_sn_terminal, dim3(g), dim3(256), 0, st, njobs, job_row_base, job_n, start_scan, xsup_all);
+    return hipGetLastError();
+}
+
+}  // namespace gsofa

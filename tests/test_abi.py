@@ -1,0 +1,120 @@
+"""The C-ABI library: it loads, exports every declared entry point, the
+binding's struct layouts match the header, and argument errors are reported
+without touching a GPU. CPU only."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "gsofa.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"GSOFA_API\s+[\w\s\*]*?\b(gsofa_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2007_00840_amd as g
+    if not os.path.exists(g.LIB_PATH):
+        from paper_2007_00840_amd import _build
+        _build.build(force=False)
+    g.load()
+    return g
+
+
+def test_exports_every_declared_symbol(g):
+    decl = _declared()
+    assert len(decl) == 9 and set(decl) == set(g.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", g.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (gsofa_\w+)", out))
+    assert set(decl) <= exported
+    lib = ctypes.CDLL(g.LIB_PATH)
+    for name in decl:
+        assert getattr(lib, name)
+
+
+def test_struct_layout_matches_header(g, tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include "gsofa.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gsofa_opts),'
+                   ' sizeof(gsofa_result), sizeof(gsofa_stats), sizeof(gsofa_csr),'
+                   ' offsetof(gsofa_result, stats), offsetof(gsofa_result, xsup),'
+                   ' offsetof(gsofa_opts, stream));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    want = [ctypes.sizeof(g.Opts), ctypes.sizeof(g.Result), ctypes.sizeof(g.Stats),
+            ctypes.sizeof(g.Csr), g.Result.stats.offset, g.Result.xsup.offset, g.Opts.stream.offset]
+    assert got == want
+
+
+def test_strerror(g):
+    for code in range(7):
+        assert len(g.strerror(code)) > 0
+    assert g.strerror(99) == "unknown status"
+
+
+@pytest.mark.parametrize("case", ["neg_n", "bad_first", "non_monotone", "col_range", "duplicate",
+                                  "neg_col"])
+def test_invalid_csr_rejected_on_host(g, case):
+    n = 4
+    rp = np.array([0, 2, 3, 5, 6], dtype=np.int32)
+    ci = np.array([0, 1, 1, 2, 3, 3], dtype=np.int32)
+    if case == "neg_n":
+        n = -1
+    elif case == "bad_first":
+        rp = rp + 1
+    elif case == "non_monotone":
+        rp = np.array([0, 3, 2, 5, 6], dtype=np.int32)
+    elif case == "col_range":
+        ci = ci.copy(); ci[3] = 4
+    elif case == "duplicate":
+        ci = np.array([0, 0, 1, 2, 3, 3], dtype=np.int32)
+    elif case == "neg_col":
+        ci = ci.copy(); ci[0] = -1
+    with pytest.raises(g.GsofaError) as e:
+        g.symbolic(n, rp, ci)
+    assert e.value.code == g.EINVAL
+
+
+def test_bad_opts_rejected(g):
+    rp = np.array([0, 1], dtype=np.int32)
+    ci = np.array([0], dtype=np.int32)
+    for kw in ({"window": -1}, {"mem_budget_bytes": -5}, {"concurrent_sources": -2}):
+        with pytest.raises(g.GsofaError) as e:
+            g.symbolic(1, rp, ci, **kw)
+        assert e.value.code == g.EINVAL
+    lib = g.load()
+    o = g.make_opts()
+    o.struct_size = 4  # too small for this ABI
+    out = ctypes.POINTER(g.Result)()
+    assert lib.gsofa_symbolic(1, rp.ctypes.data, ci.ctypes.data, ctypes.byref(o),
+                              ctypes.byref(out)) == g.EINVAL
+    assert not out
+    o = g.make_opts()
+    o.dev_alloc = 1234
+    assert lib.gsofa_symbolic(1, rp.ctypes.data, ci.ctypes.data, ctypes.byref(o),
+                              ctypes.byref(out)) == g.EINVAL
+
+
+def test_batch_argument_errors(g):
+    lib = g.load()
+    assert lib.gsofa_batch(-1, None, None, None) == g.EINVAL
+    assert lib.gsofa_batch(2, None, None, None) == g.EINVAL
+    assert lib.gsofa_batch(0, None, None, None) == g.OK
+
+
+def test_serve_argument_errors(g):
+    lib = g.load()
+    assert lib.gsofa_serve_open(None, 1, None) == g.EINVAL
+    out = ctypes.POINTER(g.Result)()
+    assert lib.gsofa_serve_poll(None, 1, 0, ctypes.byref(out)) == g.EINVAL
+    assert lib.gsofa_serve_close(None) == g.EINVAL
