@@ -93,8 +93,8 @@ typedef struct {
                                    vertices < src (each counted once per source)          */
     uint64_t edges_gpu;         /* edges actually scanned, revisits included              */
     uint64_t peak_device_bytes; /* device working memory of this call                     */
-    double t_traverse_ms;       /* fill detection (seed + traversal)                      */
-    double t_emit_ms;           /* per-row sort, CSR assembly, L transpose                */
+    double t_traverse_ms;       /* fill-detection kernel time (seed + traversal)          */
+    double t_emit_ms;           /* pointer scans and per-row sort into CSR                */
     double t_supernode_ms;
     double t_total_ms;          /* whole call, host copies included                       */
 } gsofa_stats;

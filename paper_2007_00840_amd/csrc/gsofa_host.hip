@@ -393,7 +393,7 @@ struct Engine {
         int64_t budget = plan.budget > 0 ? plan.budget : (int64_t)(di.free_b * 0.9);
         const int64_t fixed = (int64_t)(nrows * 40 + total_nnz * 8) + (64ll << 20);
         if (budget < fixed + lay.bytes_per_slot) throw Status{GSOFA_ENOMEM};
-        int64_t want = plan.nslots > 0 ? plan.nslots : (int64_t)di.cus * 20;
+        int64_t want = plan.nslots > 0 ? plan.nslots : (int64_t)traverse_resident_slots(di.cus);
         want = std::min<int64_t>(want, std::max<int64_t>(items, 1));
         const int64_t slot_room = (budget - fixed) / 2;  // half of the rest for slots
         int64_t nslots = std::min<int64_t>(want, std::max<int64_t>(slot_room / lay.bytes_per_slot, 1));
@@ -422,12 +422,13 @@ struct Engine {
         chk(launch_zero_i32(counters.as<int32_t>(), 16, st));
         chk(launch_zero_i32(jst.as<int32_t>(), (int64_t)(sizeof(JobStats) / 4) * nj, st));
 
-        hipEvent_t ev[4];
+        // ev[0]/ev[4]: traversal kernel; ev[1]..ev[3]: assembly and supernode phases
+        hipEvent_t ev[5];
         for (auto& e : ev) chk(hipEventCreate(&e));
         struct EvGuard {
             hipEvent_t* e;
             ~EvGuard() {
-                for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
+                for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e[i]);
             }
         } evg{ev};
 
@@ -452,6 +453,7 @@ struct Engine {
         ta.flags = plan.flags;
         chk(hipEventRecord(ev[0], st));
         chk(launch_traverse(ta, st));
+        chk(hipEventRecord(ev[4], st));
 
         std::vector<JobStats> hst(nj);
         unsigned long long tail = 0;
@@ -460,6 +462,7 @@ struct Engine {
         chk(hipStreamSynchronize(st));
 
         bool overflow = false;
+        float t_trav_extra = 0;
         for (int32_t q = 0; q < nj; ++q) {
             if (hst[q].err & kErrDuplicate) jstat[ord[q]] = GSOFA_EINVAL;
             if (hst[q].err & kErrOverflow) overflow = true;
@@ -493,7 +496,12 @@ struct Engine {
             // stats were already counted for these rows in the first pass: keep a copy
             std::vector<JobStats> keep = hst;
             chk(launch_zero_i32(jst.as<int32_t>(), (int64_t)(sizeof(JobStats) / 4) * nj, st));
+            float first_ms = 0;
+            chk(hipEventElapsedTime(&first_ms, ev[0], ev[4]));
+            t_trav_extra += first_ms;
+            chk(hipEventRecord(ev[0], st));
             chk(launch_traverse(ta, st));
+            chk(hipEventRecord(ev[4], st));
             chk(hipMemcpyAsync(hst.data(), jst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, st));
             chk(hipMemcpyAsync(&tail, counters.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, st));
             chk(hipStreamSynchronize(st));
@@ -607,7 +615,8 @@ struct Engine {
         }
         float t_trav = 0, t_emit = 0, t_sn = 0, t_l = 0;
         chk(hipEventSynchronize(ev[3]));
-        chk(hipEventElapsedTime(&t_trav, ev[0], ev[1]));
+        chk(hipEventElapsedTime(&t_trav, ev[0], ev[4]));
+        t_trav += t_trav_extra;
         chk(hipEventElapsedTime(&t_emit, ev[1], ev[2]));
         chk(hipEventElapsedTime(&t_sn, ev[2], ev[3]));
         (void)t_l;
@@ -1030,7 +1039,7 @@ extern "C" GSOFA_API int gsofa_serve_open(const gsofa_opts* opts, int32_t max_in
     try {
         (void)hipGetDevice(&s->device);
         DeviceInfo di = device_info();
-        s->slots_total = di.cus * 20;
+        s->slots_total = traverse_resident_slots(di.cus);
         s->budget = s->opts.mem_budget_bytes > 0 ? s->opts.mem_budget_bytes : (int64_t)(di.free_b * 0.85);
         s->streams.assign(s->max_inflight, nullptr);
         for (auto& st : s->streams) chk(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));

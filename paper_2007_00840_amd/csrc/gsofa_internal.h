@@ -78,6 +78,8 @@ hipError_t launch_validate(const Job* jobs_dev, int32_t njobs, int64_t max_n,
                            int32_t* bad_dev, hipStream_t st);
 hipError_t launch_init_slots(uint8_t* slots, int32_t nslots, SlotLayout lay, hipStream_t st);
 hipError_t launch_traverse(const TraverseArgs& a, hipStream_t st);
+// source slots that fit on the device at once (occupancy of the traversal kernel)
+int32_t traverse_resident_slots(int cus);
 hipError_t launch_row_job(const Job* jobs_dev, int32_t njobs, int64_t max_n, int32_t* row_job,
                           hipStream_t st);
 // out[0..n] = exclusive scan of (a[i] - (b ? b[i] : 0)); scratch >= scan_scratch_elems(n)

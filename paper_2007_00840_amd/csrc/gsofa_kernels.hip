@@ -66,9 +66,30 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
+// Slot state is private to the one wavefront (workgroup) that owns the slot
+// for the whole launch, so workgroup scope is enough for its loads, atomics
+// and fences: they stay in this XCD's L2 instead of going to the memory side.
+// Only the work counter, the output pool and the statistics are shared
+// across workgroups and use device-scope atomics.
 template <typename T>
-__device__ __forceinline__ T ld_coherent(const T* p) {
-    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ auto ld_coherent(T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T, typename U>
+__device__ __forceinline__ auto wg_min(T* p, U v) {
+    return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T, typename U>
+__device__ __forceinline__ auto wg_or(T* p, U v) {
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T, typename U>
+__device__ __forceinline__ auto wg_and(T* p, U v) {
+    return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T, typename U>
+__device__ __forceinline__ auto wg_xchg(T* p, U v) {
+    return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Order this wavefront's earlier global/LDS accesses before its later ones.
@@ -77,11 +98,7 @@ __device__ __forceinline__ void wave_fence() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Make this slot's plain stores visible and drop stale L1 lines.
-__device__ __forceinline__ void slot_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-    __builtin_amdgcn_wave_barrier();
-}
+__device__ __forceinline__ void slot_fence() { wave_fence(); }
 
 // Append val for every lane with pred set; count is wave-uniform.
 __device__ __forceinline__ void wave_append(bool pred, int32_t val, int32_t* buf, int32_t& count) {
@@ -206,25 +223,39 @@ struct WaveTile {
 };
 
 constexpr int kTravWaves = 4;
+constexpr int kIlp = 4;  // edges in flight per lane
+
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL T* gbl(T* p) {
+    return (GLOBAL T*)p;
+}
+
+// raw buffer view of a slot's label array: lanes whose offset is out of range
+// read 0 without touching memory, so masked label loads need no branch
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t label_rsrc(uint32_t* lab, int64_t n) {
+    return __builtin_amdgcn_make_buffer_rsrc(lab, (short)0, (int)(n * 4), 0x00020000);
+}
 
 __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
     __shared__ WaveTile tiles[kTravWaves];
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ln = lane_id();
     const int32_t slot = blockIdx.x * kTravWaves + wv;
     if (slot >= a.nslots) return;
     WaveTile& T = tiles[wv];
 
     uint8_t* sb = a.slots + (int64_t)slot * a.lay.bytes_per_slot;
-    uint32_t* lab = (uint32_t*)(sb + a.lay.off_lab);
-    uint32_t* V = (uint32_t*)(sb + a.lay.off_v);
-    unsigned long long* P = (unsigned long long*)(sb + a.lay.off_p);
-    int32_t* qa = (int32_t*)(sb + a.lay.off_qa);
-    int32_t* qb = (int32_t*)(sb + a.lay.off_qb);
-    uint32_t* qs = (uint32_t*)(sb + a.lay.off_qs);
-    int32_t* touch = (int32_t*)(sb + a.lay.off_touch);
-    int32_t* rowb = (int32_t*)(sb + a.lay.off_row);
-    uint32_t* meta = (uint32_t*)(sb + a.lay.off_meta);
+    GLOBAL uint32_t* lab = gbl((uint32_t*)(sb + a.lay.off_lab));
+    GLOBAL uint32_t* V = gbl((uint32_t*)(sb + a.lay.off_v));
+    GLOBAL unsigned long long* P = gbl((unsigned long long*)(sb + a.lay.off_p));
+    GLOBAL int32_t* qa = gbl((int32_t*)(sb + a.lay.off_qa));
+    GLOBAL int32_t* qb = gbl((int32_t*)(sb + a.lay.off_qb));
+    GLOBAL uint32_t* qs = gbl((uint32_t*)(sb + a.lay.off_qs));
+    GLOBAL int32_t* touch = gbl((int32_t*)(sb + a.lay.off_touch));
+    GLOBAL int32_t* rowb = gbl((int32_t*)(sb + a.lay.off_row));
+    GLOBAL uint32_t* meta = gbl((uint32_t*)(sb + a.lay.off_meta));
+    const __amdgpu_buffer_rsrc_t lab_r = label_rsrc((uint32_t*)(sb + a.lay.off_lab), a.lay.N);
 
     const uint32_t R = (uint32_t)a.lay.N;
     const uint32_t emax = 0xFFFFFFFFu / R;
@@ -256,8 +287,8 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
         }
         j = __builtin_amdgcn_readfirstlane(j);
         s = __builtin_amdgcn_readfirstlane(s);
-        const int32_t* rp = a.jobs[j].row_ptr;
-        const int32_t* ci = a.jobs[j].col_idx;
+        const GLOBAL int32_t* rp = gbl(a.jobs[j].row_ptr);
+        const GLOBAL int32_t* ci = gbl(a.jobs[j].col_idx);
         const int64_t grow = a.jobs[j].row_base + s;
 
         // fresh label range for this source (reset once the 32-bit range is used up)
@@ -294,16 +325,20 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
             bool fresh = false;
             if (act && w != s) {
                 const uint32_t bit = 1u << (w & 31);
-                const uint32_t old = atomicOr(&V[w >> 5], bit);
+                const uint32_t old = wg_or(&V[w >> 5], bit);
                 fresh = (old & bit) == 0;
                 dup |= !fresh;
             }
             const bool below = fresh && w < s;
-            wave_append(fresh, w, rowb, rcount);
+            {
+                unsigned long long m = __ballot(fresh);
+                if (fresh) rowb[rcount + (int32_t)lanes_below(m)] = w;
+                rcount += __popcll(m);
+            }
             lcount += __popcll(__ballot(below));
             if (below) {
                 lab[w] = base;  // label 0: no intermediate vertex
-                atomicOr(&P[w >> 6], 1ull << (w & 63));
+                wg_or(&P[w >> 6], 1ull << (w & 63));
                 e_alg += (unsigned long long)(rp[w + 1] - rp[w]);
                 pmin = min(pmin, w);
             }
@@ -341,8 +376,8 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
             ++n_win;
 
             // extract the pending vertices of [lo, hi) into the worklist
-            int32_t* cur = qa;
-            int32_t* nxt = qb;
+            GLOBAL int32_t* cur = qa;
+            GLOBAL int32_t* nxt = qb;
             int32_t qn = 0;
             const int32_t wlast = (hi - 1) >> 6;
             for (int32_t w0 = lo >> 6; w0 <= wlast; w0 += 64) {
@@ -355,7 +390,7 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
                     if (b0 < lo) m &= ~0ull << (lo - b0);
                     if (b0 + 64 > hi) m &= (hi - b0 >= 64) ? ~0ull : ((1ull << (hi - b0)) - 1ull);
                     word &= m;
-                    if (word) atomicAnd(&P[wi], ~word);
+                    if (word) wg_and(&P[wi], ~word);
                 }
                 const int c = __popcll(word);
                 const int incl = wave_incl_scan(c);
@@ -378,15 +413,11 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
                 for (int32_t c0 = 0; c0 < qn; c0 += 64) {
                     const int32_t i = c0 + ln;
                     const bool act = i < qn;
-                    int32_t fs = 0, deg = 0;
-                    uint32_t ov = kInf;
-                    if (act) {
-                        const int32_t f = ld_coherent(&cur[i]);
-                        fs = rp[f];
-                        deg = rp[f + 1] - fs;
-                        const uint32_t dl = dec(ld_coherent(&lab[f]));
-                        ov = (dl == kInf) ? kInf : max(dl, (uint32_t)f);
-                    }
+                    const int32_t f = ld_coherent(&cur[act ? i : 0]);
+                    const int32_t fs = rp[f];
+                    const int32_t deg = act ? rp[f + 1] - fs : 0;
+                    const uint32_t dl = dec(ld_coherent(&lab[f]));
+                    const uint32_t ov = (dl == kInf) ? kInf : max(dl, (uint32_t)f);
                     e_gpu += (unsigned long long)deg;
                     const int32_t incl = wave_incl_scan(deg);
                     const int32_t total = __shfl(incl, 63, 64);
@@ -394,60 +425,106 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
                     T.start[ln] = fs;
                     T.outv[ln] = ov;
                     wave_fence();
-                    for (int32_t r0 = 0; r0 < total; r0 += 64) {
-                        const int32_t ei = r0 + ln;
-                        const bool eact = ei < total;
-                        int32_t jl = 0, jh = 63;
-                        while (jl < jh) {
-                            const int32_t mid = (jl + jh) >> 1;
-                            if (T.scan[mid] > ei) jh = mid;
-                            else jl = mid + 1;
+                    // kIlp independent edges per lane per round; every load of a
+                    // round is issued before any of its results is used
+                    for (int32_t r0 = 0; r0 < total; r0 += 64 * kIlp) {
+                        int32_t w[kIlp], widx[kIlp];
+                        uint32_t outv[kIlp];
+                        bool act_e[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            const int32_t ei = r0 + kk * 64 + ln;
+                            int32_t jl = 0, jh = 63;
+                            while (jl < jh) {
+                                const int32_t mid = (jl + jh) >> 1;
+                                if (T.scan[mid] > ei) jh = mid;
+                                else jl = mid + 1;
+                            }
+                            const int32_t excl = jl ? T.scan[jl - 1] : 0;
+                            act_e[kk] = ei < total;
+                            widx[kk] = act_e[kk] ? T.start[jl] + (ei - excl) : 0;
+                            outv[kk] = T.outv[jl];
                         }
-                        const int32_t excl = jl ? T.scan[jl - 1] : 0;
-                        const int32_t w = eact ? ci[T.start[jl] + (ei - excl)] : s;
-                        const uint32_t outv = T.outv[jl];
-
-                        bool emit = false, isl = false, push = false, touched = false;
-                        if (w != s) {
-                            const uint32_t bit = 1u << (w & 31);
-                            bool settled = false;
-                            if (w > s || line95) settled = (V[w >> 5] & bit) != 0u;
-                            if (!settled) {
-                                if (w > s) {
-                                    const uint32_t old = atomicOr(&V[w >> 5], bit);
-                                    emit = (old & bit) == 0u;
-                                } else if (outv < dec(lab[w])) {
-                                    const uint32_t old = atomicMin(&lab[w], base + outv);
-                                    const uint32_t dold = dec(old);
-                                    if (outv < dold) {
-                                        if (dold == kInf)
-                                            e_alg += (unsigned long long)(rp[w + 1] - rp[w]);
-                                        if (dold >= (uint32_t)w) {
-                                            if (outv < (uint32_t)w) {
-                                                // label fell below w: fill (s, w)
-                                                emit = true;
-                                                isl = true;
-                                                atomicOr(&V[w >> 5], bit);
-                                                if (w < hi) push = true;
-                                                else atomicOr(&P[w >> 6], 1ull << (w & 63));
-                                            } else {
-                                                push = true;
-                                                touched = (dold == kInf);
-                                            }
-                                        }
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) w[kk] = ci[widx[kk]];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) w[kk] = act_e[kk] ? w[kk] : s;
+                        uint32_t vword[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) vword[kk] = V[w[kk] >> 5];
+                        bool candL[kIlp], candU[kIlp];
+                        uint32_t lv[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            const bool settled = (vword[kk] >> (w[kk] & 31)) & 1u;
+                            candU[kk] = w[kk] > s && !settled;
+                            candL[kk] = w[kk] < s && !(line95 && settled);
+                            const uint32_t off = candL[kk] ? (uint32_t)w[kk] * 4u : 0xFFFFFFF0u;
+                            lv[kk] = __builtin_amdgcn_raw_buffer_load_b32(lab_r, off, 0, 0);
+                        }
+                        // issue every returning atomic of the round before using any result
+                        uint32_t oldL[kIlp], oldU[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            candL[kk] = candL[kk] && outv[kk] < dec(lv[kk]);
+                            oldL[kk] = candL[kk] ? wg_min(&lab[w[kk]], base + outv[kk]) : kInf;
+                        }
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk)
+                            oldU[kk] = candU[kk] ? wg_or(&V[w[kk] >> 5], 1u << (w[kk] & 31)) : ~0u;
+                        bool emit[kIlp], isl[kIlp], push[kIlp], touched[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            const int32_t wk = w[kk];
+                            const uint32_t ov = outv[kk];
+                            emit[kk] = isl[kk] = push[kk] = touched[kk] = false;
+                            if (candU[kk]) emit[kk] = (oldU[kk] & (1u << (wk & 31))) == 0u;
+                            if (!candL[kk]) continue;
+                            const uint32_t dold = dec(oldL[kk]);
+                            if (ov < dold) {
+                                if (dold == kInf) e_alg += (unsigned long long)(rp[wk + 1] - rp[wk]);
+                                if (dold >= (uint32_t)wk) {
+                                    if (ov < (uint32_t)wk) {
+                                        // label fell below w: fill (s, w)
+                                        emit[kk] = true;
+                                        isl[kk] = true;
+                                        wg_or(&V[wk >> 5], 1u << (wk & 31));
+                                        if (wk < hi) push[kk] = true;
+                                        else wg_or(&P[wk >> 6], 1ull << (wk & 63));
+                                    } else {
+                                        push[kk] = true;
+                                        touched[kk] = (dold == kInf);
                                     }
                                 }
                             }
                         }
-                        if (push) push = atomicExch(&qs[w], lvl) != lvl;
-                        wave_append(emit, w, rowb, rcount);
-                        lcount += __popcll(__ballot(isl));
-                        wave_append(push, w, nxt, nq);
-                        wave_append(touched, w, touch, tcount);
+                        uint32_t stamp[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) stamp[kk] = push[kk] ? wg_xchg(&qs[w[kk]], lvl) : lvl;
+                        bool any = false;
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            push[kk] = push[kk] && stamp[kk] != lvl;
+                            any |= emit[kk] | push[kk] | touched[kk];
+                        }
+                        if (__ballot(any) == 0ull) continue;
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            unsigned long long m = __ballot(emit[kk]);
+                            if (emit[kk]) rowb[rcount + (int32_t)lanes_below(m)] = w[kk];
+                            rcount += __popcll(m);
+                            lcount += __popcll(__ballot(isl[kk]));
+                            m = __ballot(push[kk]);
+                            if (push[kk]) nxt[nq + (int32_t)lanes_below(m)] = w[kk];
+                            nq += __popcll(m);
+                            m = __ballot(touched[kk]);
+                            if (touched[kk]) touch[tcount + (int32_t)lanes_below(m)] = w[kk];
+                            tcount += __popcll(m);
+                        }
                     }
                     wave_fence();
                 }
-                int32_t* t = cur;
+                GLOBAL int32_t* t = cur;
                 cur = nxt;
                 nxt = t;
                 qn = nq;
@@ -456,7 +533,7 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
             // everything reached in this window is final now
             for (int32_t i = tmark + ln; i < tcount; i += 64) {
                 const int32_t v = ld_coherent(&touch[i]);
-                atomicOr(&V[v >> 5], 1u << (v & 31));
+                wg_or(&V[v >> 5], 1u << (v & 31));
             }
             pos = hi;
         }
@@ -469,8 +546,9 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
         if (ln == 0) off = atomicAdd(a.pool_tail, (unsigned long long)rcount);
         off = __shfl(off, 0, 64);
         const bool fits = (int64_t)(off + rcount) <= a.pool_cap;
+        GLOBAL int32_t* pool = gbl(a.pool);
         if (fits)
-            for (int32_t i = ln; i < rcount; i += 64) a.pool[off + i] = ld_coherent(&rowb[i]);
+            for (int32_t i = ln; i < rcount; i += 64) pool[off + i] = ld_coherent(&rowb[i]);
         if (ln == 0) {
             a.row_off[grow] = fits ? (int64_t)off : -1;
             a.row_cnt[grow] = rcount;
@@ -495,6 +573,16 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
         meta[0] = epoch;
         meta[1] = lvl;
     }
+}
+
+int32_t traverse_resident_slots(int cus) {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse, 64 * kTravWaves, 0) != hipSuccess ||
+        blocks <= 0) {
+        (void)hipGetLastError();
+        blocks = 4;
+    }
+    return blocks * kTravWaves * cus;
 }
 
 hipError_t launch_traverse(const TraverseArgs& a, hipStream_t st) {
