@@ -37,9 +37,9 @@ constexpr int32_t kErrOverflow = 2;
 // Working state of one source slot (one wavefront). N = largest n of the launch.
 struct SlotLayout {
     int64_t N;
-    int64_t nw32;             // 32-bit words of the settled bitmap
     int64_t nw64;             // 64-bit words of the pending bitmap
-    int64_t off_lab, off_v, off_p, off_qa, off_qb, off_qs, off_touch, off_row, off_meta;
+    int64_t qcap;             // worklist capacity
+    int64_t off_lab, off_p, off_qs, off_qa, off_qb, off_row, off_meta;
     int64_t bytes_per_slot;
 };
 

@@ -116,7 +116,6 @@ SlotLayout slot_layout(int64_t N) {
     SlotLayout L{};
     if (N < 1) N = 1;
     L.N = N;
-    L.nw32 = (N + 31) / 32;
     L.nw64 = (N + 63) / 64;
     int64_t o = 0;
     auto take = [&](int64_t bytes) {
@@ -124,14 +123,13 @@ SlotLayout slot_layout(int64_t N) {
         o += (bytes + 255) & ~int64_t(255);
         return r;
     };
+    L.qcap = N + 2048;
     L.off_lab = take(4 * N);
-    L.off_v = take(4 * L.nw32);
     L.off_p = take(8 * L.nw64);
     L.off_qs = take(4 * N);
     L.off_meta = take(64);
-    L.off_qa = take(4 * N);
-    L.off_qb = take(4 * N);
-    L.off_touch = take(4 * N);
+    L.off_qa = take(4 * L.qcap);
+    L.off_qb = take(4 * L.qcap);
     L.off_row = take(4 * N);
     L.bytes_per_slot = o;
     return L;
@@ -139,16 +137,16 @@ SlotLayout slot_layout(int64_t N) {
 
 // ------------------------------------------------------------ slot init
 
-// lab = all ones, V = P = qs = meta = 0 (everything before off_qa).
+// lab = all ones, P = qs = meta = 0 (everything before off_qa).
 __global__ void k_init_slots(uint8_t* slots, int32_t nslots, SlotLayout lay) {
     const int64_t words_lab = lay.N;
-    const int64_t words_rest = (lay.off_qa - lay.off_v) / 4;
+    const int64_t words_rest = (lay.off_qa - lay.off_p) / 4;
     for (int64_t sl = blockIdx.y; sl < nslots; sl += gridDim.y) {
         uint32_t* base = (uint32_t*)(slots + sl * lay.bytes_per_slot);
         for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words_lab;
              i += (int64_t)gridDim.x * blockDim.x)
             base[i] = kInf;
-        uint32_t* rest = (uint32_t*)(slots + sl * lay.bytes_per_slot + lay.off_v);
+        uint32_t* rest = (uint32_t*)(slots + sl * lay.bytes_per_slot + lay.off_p);
         for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words_rest;
              i += (int64_t)gridDim.x * blockDim.x)
             rest[i] = 0u;
@@ -157,7 +155,7 @@ __global__ void k_init_slots(uint8_t* slots, int32_t nslots, SlotLayout lay) {
 
 hipError_t launch_init_slots(uint8_t* slots, int32_t nslots, SlotLayout lay, hipStream_t st) {
     if (nslots <= 0) return hipSuccess;
-    int64_t words = lay.N + (lay.off_qa - lay.off_v) / 4;
+    int64_t words = lay.N + (lay.off_qa - lay.off_p) / 4;
     int gx = (int)std::min<int64_t>((words + 255) / 256, 64);
     int gy = std::min(nslots, 4096);
     hipLaunchKernelGGL(k_init_slots, dim3(gx, gy), dim3(256), 0, st, slots, nslots, lay);
@@ -223,7 +221,8 @@ struct WaveTile {
 };
 
 constexpr int kTravWaves = 4;
-constexpr int kIlp = 4;  // edges in flight per lane
+constexpr int kIlp = 4;          // edges in flight per lane
+constexpr int kHashBits = 9;     // per-wavefront push filter: 512 (level, vertex) entries
 
 #define GLOBAL __attribute__((address_space(1)))
 template <typename T>
@@ -231,29 +230,33 @@ __device__ __forceinline__ GLOBAL T* gbl(T* p) {
     return (GLOBAL T*)p;
 }
 
-// raw buffer view of a slot's label array: lanes whose offset is out of range
-// read 0 without touching memory, so masked label loads need no branch
+// raw buffer view of a slot's label array (range-checked loads)
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t label_rsrc(uint32_t* lab, int64_t n) {
     return __builtin_amdgcn_make_buffer_rsrc(lab, (short)0, (int)(n * 4), 0x00020000);
 }
 
+// The label word of a vertex carries all per-source state:
+//   stale (older source)          -> not reached yet
+//   base + x, x < v               -> v is in the structure (x = 0: original entry)
+//   base + x, x > v               -> reached through intermediates up to x, not (yet) a fill
+// For w > s the first atomic minimum that finds a stale word marks the U entry.
 __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
     __shared__ WaveTile tiles[kTravWaves];
+    __shared__ unsigned long long pushed[kTravWaves][1 << kHashBits];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ln = lane_id();
     const int32_t slot = blockIdx.x * kTravWaves + wv;
     if (slot >= a.nslots) return;
     WaveTile& T = tiles[wv];
+    unsigned long long* H = pushed[wv];
 
     uint8_t* sb = a.slots + (int64_t)slot * a.lay.bytes_per_slot;
     GLOBAL uint32_t* lab = gbl((uint32_t*)(sb + a.lay.off_lab));
-    GLOBAL uint32_t* V = gbl((uint32_t*)(sb + a.lay.off_v));
     GLOBAL unsigned long long* P = gbl((unsigned long long*)(sb + a.lay.off_p));
     GLOBAL int32_t* qa = gbl((int32_t*)(sb + a.lay.off_qa));
     GLOBAL int32_t* qb = gbl((int32_t*)(sb + a.lay.off_qb));
-    GLOBAL uint32_t* qs = gbl((uint32_t*)(sb + a.lay.off_qs));
-    GLOBAL int32_t* touch = gbl((int32_t*)(sb + a.lay.off_touch));
     GLOBAL int32_t* rowb = gbl((int32_t*)(sb + a.lay.off_row));
+    GLOBAL uint32_t* qs = gbl((uint32_t*)(sb + a.lay.off_qs));
     GLOBAL uint32_t* meta = gbl((uint32_t*)(sb + a.lay.off_meta));
     const __amdgpu_buffer_rsrc_t lab_r = label_rsrc((uint32_t*)(sb + a.lay.off_lab), a.lay.N);
 
@@ -263,6 +266,7 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
     uint32_t lvl = meta[1];
     const bool line95 = (a.flags & GSOFA_NO_LINE95) == 0;
     const int32_t D = a.window > 0 ? a.window : 1;
+    for (int i = ln; i < (1 << kHashBits); i += 64) H[i] = ~0ull;
 
     for (;;) {
         unsigned long long k = 0;
@@ -298,6 +302,7 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
             slot_fence();
         }
         if (lvl >= 0xF0000000u) {
+            for (int i = ln; i < (1 << kHashBits); i += 64) H[i] = ~0ull;
             for (int64_t i = ln; i < (int64_t)R; i += 64) qs[i] = 0u;
             lvl = 0;
             slot_fence();
@@ -309,7 +314,7 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
         };
 
         unsigned long long e_alg = 0, e_gpu = 0;
-        int32_t rcount = 0, lcount = 0, tcount = 0;
+        int32_t rcount = 0, lcount = 0;
         uint32_t n_iter = 0, n_win = 0;
 
         // ---- seed: the source row's own entries (original entries of row s)
@@ -324,9 +329,8 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
             ndiag += __popcll(__ballot(act && w == s));
             bool fresh = false;
             if (act && w != s) {
-                const uint32_t bit = 1u << (w & 31);
-                const uint32_t old = wg_or(&V[w >> 5], bit);
-                fresh = (old & bit) == 0;
+                const uint32_t old = wg_min(&lab[w], base);  // label 0: no intermediate vertex
+                fresh = dec(old) != 0u;
                 dup |= !fresh;
             }
             const bool below = fresh && w < s;
@@ -337,7 +341,6 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
             }
             lcount += __popcll(__ballot(below));
             if (below) {
-                lab[w] = base;  // label 0: no intermediate vertex
                 wg_or(&P[w >> 6], 1ull << (w & 63));
                 e_alg += (unsigned long long)(rp[w + 1] - rp[w]);
                 pmin = min(pmin, w);
@@ -402,7 +405,6 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
                 }
                 qn += __shfl(incl, 63, 64);
             }
-            const int32_t tmark = tcount;
             wave_fence();
 
             // breadth-first label correction inside the window
@@ -410,6 +412,10 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
                 ++lvl;
                 ++n_iter;
                 int32_t nq = 0;
+                // the LDS filter is exact until two vertices of this level collide in
+                // it; from then on this level also checks the per-vertex stamps, which
+                // bounds the next queue by N + 2 * (1 << kHashBits)
+                bool exact = false;
                 for (int32_t c0 = 0; c0 < qn; c0 += 64) {
                     const int32_t i = c0 + ln;
                     const bool act = i < qn;
@@ -447,65 +453,79 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
                         }
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) w[kk] = ci[widx[kk]];
-#pragma unroll
-                        for (int kk = 0; kk < kIlp; ++kk) w[kk] = act_e[kk] ? w[kk] : s;
-                        uint32_t vword[kIlp];
-#pragma unroll
-                        for (int kk = 0; kk < kIlp; ++kk) vword[kk] = V[w[kk] >> 5];
-                        bool candL[kIlp], candU[kIlp];
                         uint32_t lv[kIlp];
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
-                            const bool settled = (vword[kk] >> (w[kk] & 31)) & 1u;
-                            candU[kk] = w[kk] > s && !settled;
-                            candL[kk] = w[kk] < s && !(line95 && settled);
-                            const uint32_t off = candL[kk] ? (uint32_t)w[kk] * 4u : 0xFFFFFFF0u;
+                            act_e[kk] = act_e[kk] && w[kk] != s;
+                            const uint32_t off = act_e[kk] ? (uint32_t)w[kk] * 4u : 0xFFFFFFF0u;
                             lv[kk] = __builtin_amdgcn_raw_buffer_load_b32(lab_r, off, 0, 0);
                         }
-                        // issue every returning atomic of the round before using any result
-                        uint32_t oldL[kIlp], oldU[kIlp];
+                        // which edges can change a label: U side unseen, or a smaller value
+                        bool cand[kIlp];
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
-                            candL[kk] = candL[kk] && outv[kk] < dec(lv[kk]);
-                            oldL[kk] = candL[kk] ? wg_min(&lab[w[kk]], base + outv[kk]) : kInf;
+                            const uint32_t d = dec(lv[kk]);
+                            if (w[kk] > s) cand[kk] = act_e[kk] && d == kInf;
+                            else cand[kk] = act_e[kk] && outv[kk] < d && !(line95 && d < (uint32_t)w[kk]);
                         }
+                        uint32_t old[kIlp];
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk)
-                            oldU[kk] = candU[kk] ? wg_or(&V[w[kk] >> 5], 1u << (w[kk] & 31)) : ~0u;
-                        bool emit[kIlp], isl[kIlp], push[kIlp], touched[kIlp];
+                            old[kk] = cand[kk] ? wg_min(&lab[w[kk]], base + (w[kk] > s ? 0u : outv[kk])) : base;
+                        bool emit[kIlp], isl[kIlp], push[kIlp], first[kIlp];
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
                             const int32_t wk = w[kk];
                             const uint32_t ov = outv[kk];
-                            emit[kk] = isl[kk] = push[kk] = touched[kk] = false;
-                            if (candU[kk]) emit[kk] = (oldU[kk] & (1u << (wk & 31))) == 0u;
-                            if (!candL[kk]) continue;
-                            const uint32_t dold = dec(oldL[kk]);
-                            if (ov < dold) {
-                                if (dold == kInf) e_alg += (unsigned long long)(rp[wk + 1] - rp[wk]);
-                                if (dold >= (uint32_t)wk) {
-                                    if (ov < (uint32_t)wk) {
-                                        // label fell below w: fill (s, w)
-                                        emit[kk] = true;
-                                        isl[kk] = true;
-                                        wg_or(&V[wk >> 5], 1u << (wk & 31));
-                                        if (wk < hi) push[kk] = true;
-                                        else wg_or(&P[wk >> 6], 1ull << (wk & 63));
-                                    } else {
-                                        push[kk] = true;
-                                        touched[kk] = (dold == kInf);
-                                    }
+                            const uint32_t dold = dec(old[kk]);
+                            emit[kk] = isl[kk] = push[kk] = false;
+                            first[kk] = cand[kk] && wk < s && dold == kInf;
+                            if (!cand[kk]) continue;
+                            if (wk > s) {
+                                emit[kk] = dold == kInf;
+                                continue;
+                            }
+                            if (ov < dold && dold >= (uint32_t)wk) {
+                                if (ov < (uint32_t)wk) {
+                                    // label fell below w: fill (s, w)
+                                    emit[kk] = true;
+                                    isl[kk] = true;
+                                    if (wk < hi) push[kk] = true;
+                                    else wg_or(&P[wk >> 6], 1ull << (wk & 63));
+                                } else {
+                                    push[kk] = true;
                                 }
                             }
                         }
-                        uint32_t stamp[kIlp];
+                        // vertices reached for the first time contribute their degree
+                        int32_t fdeg[kIlp];
 #pragma unroll
-                        for (int kk = 0; kk < kIlp; ++kk) stamp[kk] = push[kk] ? wg_xchg(&qs[w[kk]], lvl) : lvl;
+                        for (int kk = 0; kk < kIlp; ++kk)
+                            fdeg[kk] = first[kk] ? rp[w[kk] + 1] - rp[w[kk]] : 0;
+                        // drop repeated pushes of a vertex within one level
+                        bool evict = false;
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            if (push[kk]) {
+                                const unsigned long long key = ((unsigned long long)lvl << 32) | (uint32_t)w[kk];
+                                const uint32_t h = ((uint32_t)w[kk] * 2654435761u) >> (32 - kHashBits);
+                                const unsigned long long prev = __hip_atomic_exchange(
+                                    &H[h], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                                push[kk] = prev != key;
+                                evict |= push[kk] && (uint32_t)(prev >> 32) == lvl;
+                            }
+                        }
+                        if (exact) {
+#pragma unroll
+                            for (int kk = 0; kk < kIlp; ++kk)
+                                if (push[kk]) push[kk] = wg_xchg(&qs[w[kk]], lvl) != lvl;
+                        }
+                        exact = exact || __ballot(evict) != 0ull;
                         bool any = false;
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
-                            push[kk] = push[kk] && stamp[kk] != lvl;
-                            any |= emit[kk] | push[kk] | touched[kk];
+                            e_alg += (unsigned long long)fdeg[kk];
+                            any |= emit[kk] | push[kk];
                         }
                         if (__ballot(any) == 0ull) continue;
 #pragma unroll
@@ -517,9 +537,6 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
                             m = __ballot(push[kk]);
                             if (push[kk]) nxt[nq + (int32_t)lanes_below(m)] = w[kk];
                             nq += __popcll(m);
-                            m = __ballot(touched[kk]);
-                            if (touched[kk]) touch[tcount + (int32_t)lanes_below(m)] = w[kk];
-                            tcount += __popcll(m);
                         }
                     }
                     wave_fence();
@@ -530,15 +547,10 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
                 qn = nq;
                 wave_fence();
             }
-            // everything reached in this window is final now
-            for (int32_t i = tmark + ln; i < tcount; i += 64) {
-                const int32_t v = ld_coherent(&touch[i]);
-                wg_or(&V[v >> 5], 1u << (v & 31));
-            }
             pos = hi;
         }
 
-        // ---- finish the row: diagonal, copy to the pool, clear the bitmaps
+        // ---- finish the row: diagonal, copy to the pool
         if (ln == 0) rowb[rcount] = s;
         rcount += 1;
         slot_fence();
@@ -555,8 +567,6 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
             a.row_lcnt[grow] = lcount;
             if (!fits) atomicOr(&a.jstats[j].err, kErrOverflow);
         }
-        for (int32_t i = ln; i < rcount; i += 64) V[ld_coherent(&rowb[i]) >> 5] = 0u;
-        for (int32_t i = ln; i < tcount; i += 64) V[ld_coherent(&touch[i]) >> 5] = 0u;
 
         e_alg = wave_sum_u64(e_alg);
         e_gpu = wave_sum_u64(e_gpu);
