@@ -74,6 +74,10 @@ typedef enum {
 #define GSOFA_LEVEL_ORDER       0x20u /* ablation: the paper's breadth-first frontier
                                          order instead of windowed order; results are
                                          unchanged, work grows                        */
+/* traversal mapping (tuning knob, results unchanged); none set -> automatic */
+#define GSOFA_MAP_WAVE          0x40u  /* one wavefront per source row                 */
+#define GSOFA_MAP_WG8           0x80u  /* eight wavefronts per source row              */
+#define GSOFA_MAP_WG16          0x100u /* sixteen wavefronts per source row            */
 
 /* A CSR pattern: n rows, row_ptr[n+1], col_idx[row_ptr[n]]; host pointers
  * unless GSOFA_INPUT_ON_DEVICE is set. */

@@ -25,6 +25,9 @@ RESULT_ON_DEVICE = 0x4
 INPUT_ON_DEVICE = 0x8
 NO_LINE95 = 0x10
 LEVEL_ORDER = 0x20
+MAP_WAVE = 0x40
+MAP_WG8 = 0x80
+MAP_WG16 = 0x100
 
 EXPORTED = ["gsofa_symbolic", "gsofa_batch", "gsofa_serve_open", "gsofa_serve_submit",
             "gsofa_serve_poll", "gsofa_serve_close", "gsofa_result_free", "gsofa_strerror",

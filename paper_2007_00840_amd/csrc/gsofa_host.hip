@@ -251,6 +251,16 @@ struct Plan {
     int64_t budget;
 };
 
+// Traversal mapping: a workgroup per source keeps fewer sources in flight, so
+// each keeps more of its XCD's L2 for its labels; tiny matrices keep one
+// wavefront per source.
+int choose_mapping(uint32_t flags, int64_t N) {
+    if (flags & GSOFA_MAP_WG16) return 1;
+    if (flags & GSOFA_MAP_WG8) return 2;
+    if (flags & GSOFA_MAP_WAVE) return 0;
+    return N >= 16384 ? 1 : 0;
+}
+
 int32_t auto_window(int64_t N) {
     // Window span for the traversal schedule. Small spans keep revisits low,
     // wider ones give fuller wavefronts; 16 was the best measured trade-off on
@@ -393,13 +403,14 @@ struct Engine {
         int64_t budget = plan.budget > 0 ? plan.budget : (int64_t)(di.free_b * 0.9);
         const int64_t fixed = (int64_t)(nrows * 40 + total_nnz * 8) + (64ll << 20);
         if (budget < fixed + lay.bytes_per_slot) throw Status{GSOFA_ENOMEM};
-        int64_t want = plan.nslots > 0 ? plan.nslots : (int64_t)traverse_resident_slots(di.cus);
+        const int mapping = choose_mapping(plan.flags, N);
+        int64_t want = plan.nslots > 0 ? plan.nslots : (int64_t)traverse_resident_slots(di.cus, mapping);
         want = std::min<int64_t>(want, std::max<int64_t>(items, 1));
         const int64_t slot_room = (budget - fixed) / 2;  // half of the rest for slots
         int64_t nslots = std::min<int64_t>(want, std::max<int64_t>(slot_room / lay.bytes_per_slot, 1));
         nslots = std::max<int64_t>(nslots, 1);
-        // round to whole blocks of 4 wavefronts
-        if (nslots > 4) nslots = nslots / 4 * 4;
+        // the one-wavefront mapping launches whole blocks of 4 wavefronts
+        if (mapping == 0 && nslots > 4) nslots = nslots / 4 * 4;
 
         int64_t pool_cap = std::max<int64_t>((int64_t)(g_fill_ratio.load() * (double)total_nnz * 1.15) + nrows,
                                              1 << 20);
@@ -451,6 +462,7 @@ struct Engine {
         ta.jstats = jst.as<JobStats>();
         ta.window = plan.window;
         ta.flags = plan.flags;
+        ta.mapping = mapping;
         chk(hipEventRecord(ev[0], st));
         chk(launch_traverse(ta, st));
         chk(hipEventRecord(ev[4], st));
@@ -1039,7 +1051,7 @@ extern "C" GSOFA_API int gsofa_serve_open(const gsofa_opts* opts, int32_t max_in
     try {
         (void)hipGetDevice(&s->device);
         DeviceInfo di = device_info();
-        s->slots_total = traverse_resident_slots(di.cus);
+        s->slots_total = traverse_resident_slots(di.cus, 0);
         s->budget = s->opts.mem_budget_bytes > 0 ? s->opts.mem_budget_bytes : (int64_t)(di.free_b * 0.85);
         s->streams.assign(s->max_inflight, nullptr);
         for (auto& st : s->streams) chk(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));

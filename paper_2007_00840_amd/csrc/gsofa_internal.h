@@ -64,6 +64,7 @@ struct TraverseArgs {
     JobStats* jstats;
     int32_t window;                   // threshold-window span in vertex ids
     uint32_t flags;
+    int32_t mapping;                  // 0: one wavefront per source; 1: 16, 2: 8 wavefronts
 };
 
 // Row-space description shared by the assembly kernels. With one job,
@@ -79,7 +80,7 @@ hipError_t launch_validate(const Job* jobs_dev, int32_t njobs, int64_t max_n,
 hipError_t launch_init_slots(uint8_t* slots, int32_t nslots, SlotLayout lay, hipStream_t st);
 hipError_t launch_traverse(const TraverseArgs& a, hipStream_t st);
 // source slots that fit on the device at once (occupancy of the traversal kernel)
-int32_t traverse_resident_slots(int cus);
+int32_t traverse_resident_slots(int cus, int mapping);
 hipError_t launch_row_job(const Job* jobs_dev, int32_t njobs, int64_t max_n, int32_t* row_job,
                           hipStream_t st);
 // out[0..n] = exclusive scan of (a[i] - (b ? b[i] : 0)); scratch >= scan_scratch_elems(n)

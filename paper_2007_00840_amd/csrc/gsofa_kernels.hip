@@ -54,6 +54,12 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     return v;
 }
 
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int d = 32; d; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
 __device__ __forceinline__ int wave_min(int v) {
 #pragma unroll
     for (int d = 32; d; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
@@ -427,30 +433,10 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
                     e_gpu += (unsigned long long)deg;
                     const int32_t incl = wave_incl_scan(deg);
                     const int32_t total = __shfl(incl, 63, 64);
-                    T.scan[ln] = incl;
-                    T.start[ln] = fs;
-                    T.outv[ln] = ov;
-                    wave_fence();
-                    // kIlp independent edges per lane per round; every load of a
+                    // one round: kIlp independent edges per lane; every load of the
                     // round is issued before any of its results is used
-                    for (int32_t r0 = 0; r0 < total; r0 += 64 * kIlp) {
-                        int32_t w[kIlp], widx[kIlp];
-                        uint32_t outv[kIlp];
-                        bool act_e[kIlp];
-#pragma unroll
-                        for (int kk = 0; kk < kIlp; ++kk) {
-                            const int32_t ei = r0 + kk * 64 + ln;
-                            int32_t jl = 0, jh = 63;
-                            while (jl < jh) {
-                                const int32_t mid = (jl + jh) >> 1;
-                                if (T.scan[mid] > ei) jh = mid;
-                                else jl = mid + 1;
-                            }
-                            const int32_t excl = jl ? T.scan[jl - 1] : 0;
-                            act_e[kk] = ei < total;
-                            widx[kk] = act_e[kk] ? T.start[jl] + (ei - excl) : 0;
-                            outv[kk] = T.outv[jl];
-                        }
+                    auto round = [&](int32_t (&widx)[kIlp], uint32_t (&outv)[kIlp], bool (&act_e)[kIlp]) {
+                        int32_t w[kIlp];
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) w[kk] = ci[widx[kk]];
                         uint32_t lv[kIlp];
@@ -527,7 +513,7 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
                             e_alg += (unsigned long long)fdeg[kk];
                             any |= emit[kk] | push[kk];
                         }
-                        if (__ballot(any) == 0ull) continue;
+                        if (__ballot(any) == 0ull) return;
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
                             unsigned long long m = __ballot(emit[kk]);
@@ -537,6 +523,48 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
                             m = __ballot(push[kk]);
                             if (push[kk]) nxt[nq + (int32_t)lanes_below(m)] = w[kk];
                             nq += __popcll(m);
+                        }
+                    };
+                    const int32_t maxdeg = wave_max(deg);
+                    if (maxdeg <= 64) {
+                        // short rows: each lane walks its own frontier's row
+                        for (int32_t t0 = 0; t0 < maxdeg; t0 += kIlp) {
+                            int32_t widx[kIlp];
+                            uint32_t outv[kIlp];
+                            bool act_e[kIlp];
+#pragma unroll
+                            for (int kk = 0; kk < kIlp; ++kk) {
+                                act_e[kk] = t0 + kk < deg;
+                                widx[kk] = act_e[kk] ? fs + t0 + kk : 0;
+                                outv[kk] = ov;
+                            }
+                            round(widx, outv, act_e);
+                        }
+                    } else {
+                        // long rows: the chunk's edges are spread evenly over the lanes
+                        T.scan[ln] = incl;
+                        T.start[ln] = fs;
+                        T.outv[ln] = ov;
+                        wave_fence();
+                        for (int32_t r0 = 0; r0 < total; r0 += 64 * kIlp) {
+                            int32_t widx[kIlp];
+                            uint32_t outv[kIlp];
+                            bool act_e[kIlp];
+#pragma unroll
+                            for (int kk = 0; kk < kIlp; ++kk) {
+                                const int32_t ei = r0 + kk * 64 + ln;
+                                int32_t jl = 0, jh = 63;
+                                while (jl < jh) {
+                                    const int32_t mid = (jl + jh) >> 1;
+                                    if (T.scan[mid] > ei) jh = mid;
+                                    else jl = mid + 1;
+                                }
+                                const int32_t excl = jl ? T.scan[jl - 1] : 0;
+                                act_e[kk] = ei < total;
+                                widx[kk] = act_e[kk] ? T.start[jl] + (ei - excl) : 0;
+                                outv[kk] = T.outv[jl];
+                            }
+                            round(widx, outv, act_e);
                         }
                     }
                     wave_fence();
@@ -585,20 +613,426 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
     }
 }
 
-int32_t traverse_resident_slots(int cus) {
-    int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse, 64 * kTravWaves, 0) != hipSuccess ||
-        blocks <= 0) {
-        (void)hipGetLastError();
-        blocks = 4;
+// --------------------------------------------- workgroup-per-source variant
+//
+// The same traversal with NW wavefronts cooperating on one source: fewer
+// sources are in flight at once, so each source's labels keep a larger share
+// of its XCD's L2. Frontier chunks of 64 vertices are dealt to the
+// wavefronts; queue and row appends go through LDS counters; levels end at a
+// workgroup barrier.
+
+struct WgCtl {
+    int32_t job, src, found, pmin;
+    int32_t cnt[3];        // next-queue counters, one per level modulo 3
+    int32_t exact[3];      // per-level exact-dedup flags, same indexing
+    int32_t rcount, lcount, dup, ndiag;
+    unsigned long long e_alg, e_gpu;
+};
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_traverse_wg(TraverseArgs a) {
+    constexpr int kWgHashBits = 11;
+    __shared__ WaveTile tiles[NW];
+    __shared__ unsigned long long H[1 << kWgHashBits];
+    __shared__ WgCtl C;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ln = lane_id();
+    const int tid = threadIdx.x;
+    const int32_t slot = blockIdx.x;
+    if (slot >= a.nslots) return;
+    WaveTile& T = tiles[wv];
+
+    uint8_t* sb = a.slots + (int64_t)slot * a.lay.bytes_per_slot;
+    GLOBAL uint32_t* lab = gbl((uint32_t*)(sb + a.lay.off_lab));
+    GLOBAL unsigned long long* P = gbl((unsigned long long*)(sb + a.lay.off_p));
+    GLOBAL int32_t* qa = gbl((int32_t*)(sb + a.lay.off_qa));
+    GLOBAL int32_t* qb = gbl((int32_t*)(sb + a.lay.off_qb));
+    GLOBAL int32_t* rowb = gbl((int32_t*)(sb + a.lay.off_row));
+    GLOBAL uint32_t* qs = gbl((uint32_t*)(sb + a.lay.off_qs));
+    GLOBAL uint32_t* meta = gbl((uint32_t*)(sb + a.lay.off_meta));
+    const __amdgpu_buffer_rsrc_t lab_r = label_rsrc((uint32_t*)(sb + a.lay.off_lab), a.lay.N);
+
+    const uint32_t R = (uint32_t)a.lay.N;
+    const uint32_t emax = 0xFFFFFFFFu / R;
+    uint32_t epoch = meta[0];
+    uint32_t lvl = meta[1];
+    const bool line95 = (a.flags & GSOFA_NO_LINE95) == 0;
+    const int32_t D = a.window > 0 ? a.window : 1;
+    for (int i = tid; i < (1 << kWgHashBits); i += 64 * NW) H[i] = ~0ull;
+
+    // wave-level append of val where pred holds, to buf at an LDS-reserved offset
+    auto append = [&](bool pred, int32_t val, GLOBAL int32_t* buf, int32_t* counter) {
+        const unsigned long long m = __ballot(pred);
+        if (m == 0ull) return;
+        int32_t b = 0;
+        if (ln == 0) b = atomicAdd(counter, (int32_t)__popcll(m));
+        b = __shfl(b, 0, 64);
+        if (pred) buf[b + (int32_t)lanes_below(m)] = val;
+    };
+
+    for (;;) {
+        if (tid == 0) {
+            const unsigned long long k = atomicAdd(a.item_counter, 1ull);
+            int32_t j = -1, s = 0;
+            if (k < (unsigned long long)a.nitems) {
+                if (a.item_rows) {
+                    const int64_t gr = a.item_rows[k];
+                    j = a.row_job ? a.row_job[gr] : 0;
+                    s = (int32_t)(gr - a.jobs[j].row_base);
+                } else {
+                    int32_t lo = 0, hi = a.njobs - 1;
+                    while (lo < hi) {
+                        int32_t mid = (lo + hi + 1) >> 1;
+                        if (a.jobs[mid].item_base <= (int64_t)k) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    j = lo;
+                    s = a.jobs[j].n - 1 - (int32_t)((int64_t)k - a.jobs[j].item_base);
+                }
+            }
+            C.job = j;
+            C.src = s;
+            C.rcount = C.lcount = C.dup = C.ndiag = 0;
+            C.pmin = 0x7FFFFFFF;
+            C.e_alg = C.e_gpu = 0ull;
+        }
+        __syncthreads();
+        const int32_t j = __builtin_amdgcn_readfirstlane(C.job);
+        const int32_t s = __builtin_amdgcn_readfirstlane(C.src);
+        if (j < 0) break;
+        const GLOBAL int32_t* rp = gbl(a.jobs[j].row_ptr);
+        const GLOBAL int32_t* ci = gbl(a.jobs[j].col_idx);
+        const int64_t grow = a.jobs[j].row_base + s;
+
+        if (epoch >= emax) {
+            for (int64_t i = tid; i < (int64_t)R; i += 64 * NW) lab[i] = kInf;
+            epoch = 0;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __syncthreads();
+        }
+        if (lvl >= 0xF0000000u) {
+            for (int i = tid; i < (1 << kWgHashBits); i += 64 * NW) H[i] = ~0ull;
+            for (int64_t i = tid; i < (int64_t)R; i += 64 * NW) qs[i] = 0u;
+            lvl = 0;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __syncthreads();
+        }
+        ++epoch;
+        const uint32_t base = 0xFFFFFFFFu - epoch * R;
+        auto dec = [&](uint32_t v) -> uint32_t {
+            return (v >= base && v - base < R) ? v - base : kInf;
+        };
+        unsigned long long e_alg = 0, e_gpu = 0;
+        uint32_t n_iter = 0, n_win = 0;
+
+        // ---- seed
+        const int32_t rs = rp[s], re = rp[s + 1];
+        {
+            int32_t pmin = 0x7FFFFFFF;
+            for (int32_t e0 = rs; e0 < re; e0 += 64 * NW) {
+                const int32_t e = e0 + tid;
+                const bool act = e < re;
+                const int32_t w = act ? ci[e] : -1;
+                const int32_t nd = __popcll(__ballot(act && w == s));
+                if (ln == 0 && nd) atomicAdd(&C.ndiag, nd);
+                bool fresh = false;
+                if (act && w != s) {
+                    const uint32_t old = wg_min(&lab[w], base);
+                    fresh = dec(old) != 0u;
+                    if (!fresh) C.dup = 1;
+                }
+                const bool below = fresh && w < s;
+                append(fresh, w, rowb, &C.rcount);
+                const int32_t nl = __popcll(__ballot(below));
+                if (ln == 0 && nl) atomicAdd(&C.lcount, nl);
+                if (below) {
+                    wg_or(&P[w >> 6], 1ull << (w & 63));
+                    e_alg += (unsigned long long)(rp[w + 1] - rp[w]);
+                    pmin = min(pmin, w);
+                }
+            }
+            pmin = wave_min(pmin);
+            if (ln == 0 && pmin != 0x7FFFFFFF) atomicMin(&C.pmin, pmin);
+        }
+        if (tid == 0) {
+            e_alg += (unsigned long long)(re - rs);
+            e_gpu += (unsigned long long)(re - rs);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __syncthreads();
+        if (tid == 0 && (C.dup || C.ndiag > 1)) atomicOr(&a.jstats[j].err, kErrDuplicate);
+
+        // ---- windows
+        const int32_t nwp = (s + 63) >> 6;
+        int32_t pos = __builtin_amdgcn_readfirstlane(C.pmin);
+        GLOBAL int32_t* cur = qa;
+        GLOBAL int32_t* nxt = qb;
+        while (pos < s) {
+            if (tid == 0) C.found = 0x7FFFFFFF;
+            __syncthreads();
+            for (int32_t w0 = pos >> 6; w0 < nwp; w0 += 64 * NW) {
+                const int32_t wi = w0 + tid;
+                const unsigned long long word = (wi < nwp) ? ld_coherent(&P[wi]) : 0ull;
+                if (word) atomicMin(&C.found, wi * 64 + __builtin_ctzll(word));
+                __syncthreads();
+                const int32_t got = C.found;
+                __syncthreads();  // every thread has read C.found before any may change it
+                if (got != 0x7FFFFFFF) break;
+            }
+            const int32_t found = __builtin_amdgcn_readfirstlane(C.found);
+            if (found == 0x7FFFFFFF) break;
+            const int32_t lo = found;
+            const int32_t hi = (int32_t)min((int64_t)lo + D, (int64_t)s);
+            ++n_win;
+            // extract [lo, hi) into cur
+            if (tid == 0) {
+                C.cnt[lvl % 3] = 0;
+                C.cnt[(lvl + 1) % 3] = 0;
+                C.exact[(lvl + 1) % 3] = 0;
+            }
+            __syncthreads();
+            const int32_t wlast = (hi - 1) >> 6;
+            for (int32_t w0 = lo >> 6; w0 <= wlast; w0 += 64 * NW) {
+                const int32_t wi = w0 + tid;
+                unsigned long long word = 0ull;
+                if (wi <= wlast) {
+                    word = ld_coherent(&P[wi]);
+                    const int64_t b0 = (int64_t)wi * 64;
+                    unsigned long long m = ~0ull;
+                    if (b0 < lo) m &= ~0ull << (lo - b0);
+                    if (b0 + 64 > hi) m &= (hi - b0 >= 64) ? ~0ull : ((1ull << (hi - b0)) - 1ull);
+                    word &= m;
+                    if (word) wg_and(&P[wi], ~word);
+                }
+                const int c = __popcll(word);
+                int32_t o = 0;
+                if (c) o = atomicAdd(&C.cnt[lvl % 3], c);
+                while (word) {
+                    const int b = __builtin_ctzll(word);
+                    word &= word - 1ull;
+                    cur[o++] = wi * 64 + b;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __syncthreads();
+            int32_t qn = __builtin_amdgcn_readfirstlane(C.cnt[lvl % 3]);
+
+            while (qn > 0) {
+                ++lvl;
+                ++n_iter;
+                // level lvl appends to counter lvl % 3; the one for lvl + 1 was last
+                // used two levels ago and is cleared now
+                if (tid == 0) {
+                    C.cnt[(lvl + 1) % 3] = 0;
+                    C.exact[(lvl + 1) % 3] = 0;
+                }
+                int32_t* nqc = &C.cnt[lvl % 3];
+                int32_t* exf = &C.exact[lvl % 3];
+                for (int32_t c0 = wv * 64; c0 < qn; c0 += 64 * NW) {
+                    const int32_t i = c0 + ln;
+                    const bool act = i < qn;
+                    const int32_t f = ld_coherent(&cur[act ? i : 0]);
+                    const int32_t fs = rp[f];
+                    const int32_t deg = act ? rp[f + 1] - fs : 0;
+                    const uint32_t dl = dec(ld_coherent(&lab[f]));
+                    const uint32_t ov = (dl == kInf) ? kInf : max(dl, (uint32_t)f);
+                    e_gpu += (unsigned long long)deg;
+                    const int32_t incl = wave_incl_scan(deg);
+                    const int32_t total = __shfl(incl, 63, 64);
+                    auto round = [&](int32_t (&widx)[kIlp], uint32_t (&outv)[kIlp], bool (&act_e)[kIlp]) {
+                        int32_t w[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) w[kk] = ci[widx[kk]];
+                        uint32_t lv[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            act_e[kk] = act_e[kk] && w[kk] != s;
+                            const uint32_t off = act_e[kk] ? (uint32_t)w[kk] * 4u : 0xFFFFFFF0u;
+                            lv[kk] = __builtin_amdgcn_raw_buffer_load_b32(lab_r, off, 0, 0);
+                        }
+                        bool cand[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            const uint32_t d = dec(lv[kk]);
+                            if (w[kk] > s) cand[kk] = act_e[kk] && d == kInf;
+                            else cand[kk] = act_e[kk] && outv[kk] < d && !(line95 && d < (uint32_t)w[kk]);
+                        }
+                        uint32_t old[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk)
+                            old[kk] = cand[kk] ? wg_min(&lab[w[kk]], base + (w[kk] > s ? 0u : outv[kk])) : base;
+                        bool emit[kIlp], isl[kIlp], push[kIlp], first[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            const int32_t wk = w[kk];
+                            const uint32_t o2 = outv[kk];
+                            const uint32_t dold = dec(old[kk]);
+                            emit[kk] = isl[kk] = push[kk] = false;
+                            first[kk] = cand[kk] && wk < s && dold == kInf;
+                            if (!cand[kk]) continue;
+                            if (wk > s) {
+                                emit[kk] = dold == kInf;
+                                continue;
+                            }
+                            if (o2 < dold && dold >= (uint32_t)wk) {
+                                if (o2 < (uint32_t)wk) {
+                                    emit[kk] = true;
+                                    isl[kk] = true;
+                                    if (wk < hi) push[kk] = true;
+                                    else wg_or(&P[wk >> 6], 1ull << (wk & 63));
+                                } else {
+                                    push[kk] = true;
+                                }
+                            }
+                        }
+                        int32_t fdeg[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk)
+                            fdeg[kk] = first[kk] ? rp[w[kk] + 1] - rp[w[kk]] : 0;
+                        bool evict = false;
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            if (push[kk]) {
+                                const unsigned long long key = ((unsigned long long)lvl << 32) | (uint32_t)w[kk];
+                                const uint32_t h = ((uint32_t)w[kk] * 2654435761u) >> (32 - kWgHashBits);
+                                const unsigned long long prev = __hip_atomic_exchange(
+                                    &H[h], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                push[kk] = prev != key;
+                                evict |= push[kk] && (uint32_t)(prev >> 32) == lvl;
+                            }
+                        }
+                        if (*exf) {
+#pragma unroll
+                            for (int kk = 0; kk < kIlp; ++kk)
+                                if (push[kk]) push[kk] = wg_xchg(&qs[w[kk]], lvl) != lvl;
+                        }
+                        if (__ballot(evict) != 0ull && ln == 0) *exf = 1;
+                        bool any = false;
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            e_alg += (unsigned long long)fdeg[kk];
+                            any |= emit[kk] | push[kk];
+                        }
+                        if (__ballot(any) == 0ull) return;
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            append(emit[kk], w[kk], rowb, &C.rcount);
+                            const int32_t nl = __popcll(__ballot(isl[kk]));
+                            if (ln == 0 && nl) atomicAdd(&C.lcount, nl);
+                            append(push[kk], w[kk], nxt, nqc);
+                        }
+                    };
+                    const int32_t maxdeg = wave_max(deg);
+                    if (maxdeg <= 64) {
+                        for (int32_t t0 = 0; t0 < maxdeg; t0 += kIlp) {
+                            int32_t widx[kIlp];
+                            uint32_t outv[kIlp];
+                            bool act_e[kIlp];
+#pragma unroll
+                            for (int kk = 0; kk < kIlp; ++kk) {
+                                act_e[kk] = t0 + kk < deg;
+                                widx[kk] = act_e[kk] ? fs + t0 + kk : 0;
+                                outv[kk] = ov;
+                            }
+                            round(widx, outv, act_e);
+                        }
+                    } else {
+                        T.scan[ln] = incl;
+                        T.start[ln] = fs;
+                        T.outv[ln] = ov;
+                        wave_fence();
+                        for (int32_t r0 = 0; r0 < total; r0 += 64 * kIlp) {
+                            int32_t widx[kIlp];
+                            uint32_t outv[kIlp];
+                            bool act_e[kIlp];
+#pragma unroll
+                            for (int kk = 0; kk < kIlp; ++kk) {
+                                const int32_t ei = r0 + kk * 64 + ln;
+                                int32_t jl = 0, jh = 63;
+                                while (jl < jh) {
+                                    const int32_t mid = (jl + jh) >> 1;
+                                    if (T.scan[mid] > ei) jh = mid;
+                                    else jl = mid + 1;
+                                }
+                                const int32_t excl = jl ? T.scan[jl - 1] : 0;
+                                act_e[kk] = ei < total;
+                                widx[kk] = act_e[kk] ? T.start[jl] + (ei - excl) : 0;
+                                outv[kk] = T.outv[jl];
+                            }
+                            round(widx, outv, act_e);
+                        }
+                        wave_fence();
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                __syncthreads();
+                qn = __builtin_amdgcn_readfirstlane(*nqc);
+                GLOBAL int32_t* t = cur;
+                cur = nxt;
+                nxt = t;
+            }
+            pos = hi;
+        }
+
+        // ---- finish the row
+        if (e_alg) atomicAdd(&C.e_alg, e_alg);
+        if (e_gpu) atomicAdd(&C.e_gpu, e_gpu);
+        __syncthreads();
+        const int32_t rc = __builtin_amdgcn_readfirstlane(C.rcount) + 1;
+        __shared__ unsigned long long s_off;
+        if (tid == 0) {
+            rowb[rc - 1] = s;
+            s_off = atomicAdd(a.pool_tail, (unsigned long long)rc);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __syncthreads();
+        const unsigned long long off = s_off;
+        const bool fits = (int64_t)(off + rc) <= a.pool_cap;
+        GLOBAL int32_t* pool = gbl(a.pool);
+        if (fits)
+            for (int32_t i = tid; i < rc; i += 64 * NW) pool[off + i] = ld_coherent(&rowb[i]);
+        if (tid == 0) {
+            a.row_off[grow] = fits ? (int64_t)off : -1;
+            a.row_cnt[grow] = rc;
+            a.row_lcnt[grow] = C.lcount;
+            if (!fits) atomicOr(&a.jstats[j].err, kErrOverflow);
+            atomicAdd(&a.jstats[j].edges_alg, C.e_alg);
+            atomicAdd(&a.jstats[j].edges_gpu, C.e_gpu);
+            atomicAdd(&a.jstats[j].iterations, (unsigned long long)n_iter);
+            atomicAdd(&a.jstats[j].windows, (unsigned long long)n_win);
+            if (C.ndiag > 0) atomicAdd(&a.jstats[j].diag, 1ull);
+        }
+        __syncthreads();
     }
-    return blocks * kTravWaves * cus;
+    if (tid == 0) {
+        meta[0] = epoch;
+        meta[1] = lvl;
+    }
+}
+
+int32_t traverse_resident_slots(int cus, int mapping) {
+    int blocks = 0;
+    hipError_t e;
+    if (mapping == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse_wg<16>, 64 * 16, 0);
+    else if (mapping == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse_wg<8>, 64 * 8, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse, 64 * kTravWaves, 0);
+    if (e != hipSuccess || blocks <= 0) {
+        (void)hipGetLastError();
+        blocks = 1;
+    }
+    return blocks * (mapping == 0 ? kTravWaves : 1) * cus;
 }
 
 hipError_t launch_traverse(const TraverseArgs& a, hipStream_t st) {
     if (a.nslots <= 0 || a.nitems <= 0) return hipSuccess;
-    const int blocks = (a.nslots + kTravWaves - 1) / kTravWaves;
-    hipLaunchKernelGGL(k_traverse, dim3(blocks), dim3(64 * kTravWaves), 0, st, a);
+    if (a.mapping == 1) {
+        hipLaunchKernelGGL(k_traverse_wg<16>, dim3(a.nslots), dim3(64 * 16), 0, st, a);
+    } else if (a.mapping == 2) {
+        hipLaunchKernelGGL(k_traverse_wg<8>, dim3(a.nslots), dim3(64 * 8), 0, st, a);
+    } else {
+        const int blocks = (a.nslots + kTravWaves - 1) / kTravWaves;
+        hipLaunchKernelGGL(k_traverse, dim3(blocks), dim3(64 * kTravWaves), 0, st, a);
+    }
     return hipGetLastError();
 }
 

@@ -1,0 +1,149 @@
+"""GPU parity of the batch and serve entry points against the CPU oracle and
+against the one-matrix path."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2007_00840_amd as g
+    g.load()
+    return g
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def same(res, ref):
+    return (np.array_equal(res.u_ptr, ref.u_ptr) and np.array_equal(res.u_idx, ref.u_idx)
+            and np.array_equal(res.l_ptr, ref.l_ptr) and np.array_equal(res.l_idx, ref.l_idx)
+            and res.nsuper == ref.nsuper and np.array_equal(res.xsup, ref.xsup)
+            and np.array_equal(res.supno, ref.supno) and res.stats["edges_alg"] == ref.edges_alg)
+
+
+def same_result(a, b):
+    return (np.array_equal(a.u_ptr, b.u_ptr) and np.array_equal(a.u_idx, b.u_idx)
+            and np.array_equal(a.l_ptr, b.l_ptr) and np.array_equal(a.l_idx, b.l_idx)
+            and np.array_equal(a.xsup, b.xsup) and np.array_equal(a.supno, b.supno))
+
+
+def test_batch_members_match_oracle(g):
+    ks = list(range(0, 96)) + [4095]
+    mats = [synth.batch_member(k) for k in ks]
+    _say(f"batch of {len(mats)} members, sum n = {sum(m.n for m in mats)}")
+    res = g.batch([(m.n, m.row_ptr, m.col_idx) for m in mats])
+    assert len(res) == len(mats)
+    for k, m, r in zip(ks, mats, res):
+        ref = oracle.symbolic(m.n, m.row_ptr, m.col_idx)
+        assert same(r, ref), f"member {k}"
+
+
+def test_batch_equals_single_calls_and_mixed_sizes(g):
+    mats = [synth.stencil(27, (12, 11, 10), nd=True, seed=5), synth.batch_member(3),
+            synth.stencil(9, (1, 1), nd=True, seed=1), synth.stencil(5, (60, 2), nd=False, seed=9),
+            synth.batch_member(8)]
+    empty = (0, np.zeros(1, dtype=np.int32), np.zeros(0, dtype=np.int32))
+    args = [(m.n, m.row_ptr, m.col_idx) for m in mats] + [empty]
+    for flags in (0, 0x40, 0x100):
+        res = g.batch(args, flags=flags)
+        for m, r in zip(mats, res):
+            assert same_result(r, g.symbolic(m.n, m.row_ptr, m.col_idx))
+        assert res[-1].n == 0 and res[-1].nsuper == 0
+
+
+def test_batch_reports_per_matrix_errors(g):
+    good = synth.batch_member(2)
+    bad_ci = good.col_idx.copy()
+    bad_ci[3] = good.n + 5
+    res = g.batch([(good.n, good.row_ptr, good.col_idx), (good.n, good.row_ptr, bad_ci),
+                   (good.n, good.row_ptr, good.col_idx)], raise_on_error=False)
+    assert res[1] is None
+    ref = oracle.symbolic(good.n, good.row_ptr, good.col_idx)
+    assert same(res[0], ref) and same(res[2], ref)
+    with pytest.raises(g.GsofaError) as e:
+        g.batch([(good.n, good.row_ptr, bad_ci)])
+    assert e.value.code == g.EINVAL
+
+
+def test_batch_device_inputs_and_results(g):
+    import torch
+    mats = [synth.batch_member(k) for k in (10, 11, 12)]
+    args = [(m.n, torch.from_numpy(m.row_ptr).cuda(), torch.from_numpy(m.col_idx).cuda())
+            for m in mats]
+    res = g.batch(args, flags=g.RESULT_ON_DEVICE)
+    for m, d in zip(mats, res):
+        ref = oracle.symbolic(m.n, m.row_ptr, m.col_idx)
+        t = d.to_torch()
+        assert np.array_equal(t["u_ptr"].cpu().numpy(), ref.u_ptr)
+        assert np.array_equal(t["u_idx"].cpu().numpy(), ref.u_idx)
+        assert np.array_equal(t["l_ptr"].cpu().numpy(), ref.l_ptr)
+        assert np.array_equal(t["l_idx"].cpu().numpy(), ref.l_idx)
+        assert np.array_equal(t["xsup"].cpu().numpy(), ref.xsup)
+        assert np.array_equal(t["supno"].cpu().numpy(), ref.supno)
+        d.free()
+
+
+def test_serve_results_alone_and_in_mix(g):
+    reqs = synth.serve_trace(count=12)
+    mats = [r.matrix() for r in reqs if r.n_req <= 40000][:8]
+    assert len(mats) >= 4
+    _say(f"serve: {len(mats)} requests, n = {[m.n for m in mats]}")
+    # alone: one request at a time
+    with g.Server(max_inflight=1) as srv:
+        alone = []
+        for m in mats:
+            t = srv.submit(m.n, m.row_ptr, m.col_idx)
+            alone.append(srv.poll(t, timeout_us=-1))
+    # mixed: all submitted at once, several in flight
+    with g.Server(max_inflight=4) as srv:
+        tickets = [srv.submit(m.n, m.row_ptr, m.col_idx) for m in mats]
+        mixed = {}
+        deadline = time.time() + 60
+        while len(mixed) < len(tickets) and time.time() < deadline:
+            for t in tickets:
+                if t not in mixed:
+                    r = srv.poll(t, timeout_us=1000)
+                    if r is not None:
+                        mixed[t] = r
+        assert len(mixed) == len(tickets)
+    for m, a, t in zip(mats, alone, tickets):
+        ref = oracle.symbolic(m.n, m.row_ptr, m.col_idx)
+        assert same(a, ref)
+        assert same_result(a, mixed[t])
+
+
+def test_serve_status_codes(g):
+    m = synth.stencil(27, (30, 30, 30), nd=True, seed=77)
+    with g.Server(max_inflight=2) as srv:
+        t = srv.submit(m.n, m.row_ptr, m.col_idx)
+        # immediately after submission the request cannot be done yet
+        assert srv.poll(t, timeout_us=0) is None
+        r = srv.poll(t, timeout_us=-1)
+        assert r.n == m.n
+        with pytest.raises(g.GsofaError) as e:
+            srv.poll(t, timeout_us=0)  # already collected
+        assert e.value.code == g.ENOTFOUND
+        with pytest.raises(g.GsofaError) as e:
+            srv.poll(987654, timeout_us=0)
+        assert e.value.code == g.ENOTFOUND
+        bad = m.col_idx.copy()
+        bad[0] = -3
+        with pytest.raises(g.GsofaError) as e:
+            srv.submit(m.n, m.row_ptr, bad)
+        assert e.value.code == g.EINVAL
+    with g.Server(max_inflight=1, mem_budget_bytes=1 << 20) as srv:
+        with pytest.raises(g.GsofaError) as e:
+            srv.submit(m.n, m.row_ptr, m.col_idx)
+        assert e.value.code == g.ECAPACITY

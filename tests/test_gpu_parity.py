@@ -110,8 +110,9 @@ def test_edge_sizes(g):
     assert r.nnz_u == n and r.nnz_l == 0 and r.nsuper == n and r.fills == 0
 
 
+@pytest.mark.parametrize("mapping", [0x40, 0x80, 0x100])
 @pytest.mark.parametrize("name", ["dense", "arrow_first", "arrow_last", "tril", "triu"])
-def test_closed_forms_on_gpu(g, name):
+def test_closed_forms_on_gpu(g, name, mapping):
     n = 300
     if name == "dense":
         D = np.ones((n, n), dtype=bool)
@@ -124,9 +125,9 @@ def test_closed_forms_on_gpu(g, name):
     else:
         D = np.triu(np.ones((n, n), dtype=bool))
     rp, ci = _csr_from_dense(D)
-    _say(f"closed form {name}")
+    _say(f"closed form {name} mapping={mapping:#x}")
     ref = run_ref(n, rp, ci)
-    assert_same(g.symbolic(n, rp, ci), ref)
+    assert_same(g.symbolic(n, rp, ci, flags=mapping), ref)
 
 
 def _families():
@@ -136,10 +137,12 @@ def _families():
             synth.stencil(27, (13, 11, 9), nd=True, seed=14),
             synth.stencil(7, (20, 19, 18), nd=True, seed=15),
             synth.stencil(5, (70, 70), nd=False, seed=16),
-            synth.batch_member(0), synth.batch_member(1), synth.batch_member(7)]
+            synth.batch_member(0), synth.batch_member(1), synth.batch_member(7),
+            synth.stencil(27, (27, 26, 25), nd=True, seed=17),
+            synth.stencil(9, (150, 140), nd=True, seed=18)]
 
 
-@pytest.mark.parametrize("idx", range(9))
+@pytest.mark.parametrize("idx", range(11))
 def test_generator_families(g, idx):
     m = _families()[idx]
     _say(f"family {m.desc} n={m.n}")
@@ -152,6 +155,9 @@ def test_generator_families(g, idx):
     {"flags": 0x20}, {"flags": 0x10}, {"concurrent_sources": 1}, {"concurrent_sources": 7},
     {"concurrent_sources": 64, "window": 2}, {"max_supernode": 16}, {"max_supernode": -1},
     {"max_supernode": 1}, {"flags": 0x2}, {"flags": 0x1},
+    {"flags": 0x40}, {"flags": 0x80}, {"flags": 0x100}, {"flags": 0x100 | 0x20},
+    {"flags": 0x80, "concurrent_sources": 3}, {"flags": 0x100, "window": 1},
+    {"flags": 0x80 | 0x10, "window": 64},
 ], ids=str)
 def test_knobs_do_not_change_results(g, kw):
     m = synth.stencil(27, (11, 10, 9), nd=True, seed=21)
