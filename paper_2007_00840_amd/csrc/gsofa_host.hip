@@ -251,14 +251,15 @@ struct Plan {
     int64_t budget;
 };
 
-// Traversal mapping: a workgroup per source keeps fewer sources in flight, so
-// each keeps more of its XCD's L2 for its labels; tiny matrices keep one
-// wavefront per source.
+// Traversal mapping. One wavefront per source is the default: per-source
+// frontiers are small (a window holds a few dozen vertices), so a workgroup per
+// source leaves most of its wavefronts idle and was 3-5x slower on the 64^3
+// and 1000^2 stencils. The workgroup variants stay available as tuning knobs.
 int choose_mapping(uint32_t flags, int64_t N) {
+    (void)N;
     if (flags & GSOFA_MAP_WG16) return 1;
     if (flags & GSOFA_MAP_WG8) return 2;
-    if (flags & GSOFA_MAP_WAVE) return 0;
-    return N >= 16384 ? 1 : 0;
+    return 0;
 }
 
 int32_t auto_window(int64_t N) {
