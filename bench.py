@@ -45,6 +45,134 @@ def cpu_baseline(m, stride):
                       f"{e:.3e} algorithmic edges in {dt:.1f} s"}
 
 
+def bench_batch(g, torch, synth, reps):
+    """The 4,096-matrix batch (config 4): one gsofa_batch call against one
+    gsofa_symbolic call per matrix, inputs and results in device memory."""
+    import numpy as np
+    t0 = time.perf_counter()
+    mats = [synth.batch_member(k) for k in range(synth.BATCH_COUNT)]
+    log(f"batch: generated {len(mats)} matrices in {time.perf_counter() - t0:.1f} s, "
+        f"sum n = {sum(m.n for m in mats)}")
+    dev = [(m.n, torch.from_numpy(m.row_ptr).cuda(), torch.from_numpy(m.col_idx).cuda()) for m in mats]
+    stream = torch.cuda.current_stream().cuda_stream
+    flags = g.RESULT_ON_DEVICE
+    res = g.batch(dev, flags=flags, stream=stream)  # warm-up
+    e_alg = sum(r.stats["edges_alg"] for r in res)
+    phases = {k: round(res[0].stats[k], 3) for k in ("t_traverse_ms", "t_emit_ms", "t_supernode_ms",
+                                                      "t_total_ms")}
+    phases["concurrent_sources"] = res[0].stats["concurrent_sources"]
+    for r in res:
+        r.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = g.batch(dev, flags=flags, stream=stream)
+        for r in res:
+            r.free()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for n, rp, ci in dev:
+        r = g.symbolic(n, rp, ci, flags=flags, stream=stream)
+        r.free()
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    log(f"batch: {t_batch * 1e3:.1f} ms per batch, one call per matrix {t_single * 1e3:.1f} ms, "
+        f"edges_alg {e_alg:.3e}, phases {phases}")
+    return {"matrices": len(mats), "sum_n": int(sum(m.n for m in mats)), "edges_alg": e_alg,
+            "ms_per_batch": round(t_batch * 1e3, 3),
+            "matrices_per_s": round(len(mats) / t_batch, 1),
+            "gteps": round(e_alg / t_batch / 1e9, 3),
+            "one_call_per_matrix_ms": round(t_single * 1e3, 3),
+            "one_call_per_matrix_matrices_per_s": round(len(mats) / t_single, 1),
+            "speedup_vs_one_call_per_matrix": round(t_single / t_batch, 3),
+            "phases_ms": phases}
+
+
+def _serve_run(g, synth, trace, cap_s, mode, max_outstanding=64):
+    """Offers the trace on its arrival schedule for cap_s seconds. mode 'serve'
+    uses the continuous-batching server, 'plain' one gsofa_symbolic call at a
+    time in arrival order. Latency = completion - scheduled arrival; requests
+    that arrived before the cap but did not finish count as censored."""
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+    import numpy as np
+    done_at = {}
+    pool = ThreadPoolExecutor(max_workers=8)
+    futs = {}
+    arrived = [r for r in trace if r.arrival_s <= cap_s]
+    for r in arrived[:2 * max_outstanding]:
+        futs[r.rid] = pool.submit(r.matrix)
+    t0 = time.perf_counter()
+    nxt = 0
+    if mode == "serve":
+        srv = g.Server(max_inflight=4, mem_budget_bytes=200 << 30)
+        outstanding = {}
+        while True:
+            now = time.perf_counter() - t0
+            if now > cap_s:
+                break
+            # submit everything that has arrived, within the outstanding bound
+            while (nxt < len(arrived) and arrived[nxt].arrival_s <= now
+                   and len(outstanding) < max_outstanding):
+                r = arrived[nxt]
+                m = futs.pop(r.rid).result()
+                k = nxt + 2 * max_outstanding
+                if k < len(arrived):
+                    futs[arrived[k].rid] = pool.submit(arrived[k].matrix)
+                outstanding[srv.submit(m.n, m.row_ptr, m.col_idx)] = r
+                nxt += 1
+            for t in list(outstanding):
+                res = srv.poll(t, timeout_us=0)
+                if res is not None:
+                    done_at[outstanding.pop(t).rid] = time.perf_counter() - t0
+            time.sleep(0.0005)
+        srv.close()
+    else:
+        while nxt < len(arrived):
+            now = time.perf_counter() - t0
+            if now > cap_s:
+                break
+            r = arrived[nxt]
+            if r.arrival_s > now:
+                time.sleep(min(r.arrival_s - now, 0.01))
+                continue
+            m = futs.pop(r.rid).result()
+            k = nxt + 2 * max_outstanding
+            if k < len(arrived):
+                futs[arrived[k].rid] = pool.submit(arrived[k].matrix)
+            g.symbolic(m.n, m.row_ptr, m.col_idx)
+            done_at[r.rid] = time.perf_counter() - t0
+            nxt += 1
+    pool.shutdown(wait=False, cancel_futures=True)
+    lat = np.array([done_at[r.rid] - r.arrival_s if r.rid in done_at else np.inf for r in arrived])
+    lat.sort()
+    def pct(q):
+        v = lat[min(len(lat) - 1, int(np.ceil(q * len(lat))) - 1)]
+        return round(float(v) * 1e3, 1) if np.isfinite(v) else f"> {cap_s * 1e3:.0f} (censored)"
+    return {"offered": len(arrived), "completed": len(done_at),
+            "completed_per_s": round(len(done_at) / cap_s, 2),
+            "p50_ms": pct(0.5), "p99_ms": pct(0.99),
+            "censored_frac": round(float(np.mean(~np.isfinite(lat))), 4)}
+
+
+def bench_serve(g, synth, cap_s):
+    """The request stream (config 5): Poisson arrivals at 200 requests/s,
+    n log-uniform in [1e3, 1e6], 2D 9-point or 3D 27-point, ND order, drop
+    0.2, memory budget 200 GB; offered for cap_s seconds."""
+    trace = synth.serve_trace()
+    log(f"serve: {len(trace)} requests in the 60 s trace; offering the first {cap_s:.0f} s")
+    out = {"cap_s": cap_s, "rate_per_s": synth.SERVE_RATE}
+    out["continuous_batching"] = _serve_run(g, synth, trace, cap_s, "serve")
+    log(f"serve: {out['continuous_batching']}")
+    out["plain_sequential"] = _serve_run(g, synth, trace, cap_s, "plain")
+    log(f"serve plain: {out['plain_sequential']}")
+    a = out["continuous_batching"]["completed"]
+    b = out["plain_sequential"]["completed"]
+    out["throughput_vs_plain"] = round(a / b, 3) if b else None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +183,9 @@ def main():
     ap.add_argument("--window", type=int, default=0)
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--flags", type=int, default=0)
+    ap.add_argument("--batch-reps", type=int, default=3, help="0 = skip the batch measurement")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="wall cap of the request-stream measurement (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -113,6 +244,9 @@ def main():
     log(f"steps: {ms:.1f} ms/step, traverse {t_trav:.1f} ms, emit {t_emit:.1f} ms, "
         f"supernode {t_sn:.1f} ms, {gteps:.1f} GTEPS")
 
+    batch = bench_batch(g, torch, synth, args.batch_reps) if args.batch_reps > 0 else None
+    serve = bench_serve(g, synth, args.serve_seconds) if args.serve_seconds > 0 else None
+
     base = None
     if args.cpu_stride > 0:
         log(f"cpu baseline: oracle on every {args.cpu_stride}th row ...")
@@ -148,6 +282,8 @@ def main():
         "t_traverse_ms": round(t_trav, 3), "t_emit_ms": round(t_emit, 3),
         "t_supernode_ms": round(t_sn, 3),
         "concurrent_sources": stats[-1]["concurrent_sources"],
+        "batch": batch,
+        "serve": serve,
     }
     print(json.dumps(out), flush=True)
 

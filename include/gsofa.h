@@ -74,8 +74,9 @@ typedef enum {
 #define GSOFA_LEVEL_ORDER       0x20u /* ablation: the paper's breadth-first frontier
                                          order instead of windowed order; results are
                                          unchanged, work grows                        */
-/* traversal mapping (tuning knob, results unchanged); none set -> automatic */
-#define GSOFA_MAP_WAVE          0x40u  /* one wavefront per source row                 */
+/* traversal mapping (tuning knob, results unchanged); none set -> one
+ * wavefront per source row with one state byte per vertex (windows up to 253) */
+#define GSOFA_MAP_WAVE32        0x40u  /* one wavefront per source row, 32-bit labels  */
 #define GSOFA_MAP_WG8           0x80u  /* eight wavefronts per source row              */
 #define GSOFA_MAP_WG16          0x100u /* sixteen wavefronts per source row            */
 
@@ -180,7 +181,8 @@ GSOFA_API int gsofa_batch(int32_t count, const gsofa_csr* mats, const gsofa_opts
  *     <0 = wait forever) for the ticket; GSOFA_EAGAIN if not done,
  *     GSOFA_ENOTFOUND for an unknown or collected ticket; otherwise the
  *     request's own status, with *out set on GSOFA_OK.
- *   serve_close waits for running requests and frees the server.
+ *   serve_close drops requests that were not admitted yet, waits for the
+ *     running ones and frees the server (with every uncollected result).
  */
 GSOFA_API int gsofa_serve_open(const gsofa_opts* opts, int32_t max_inflight, gsofa_server** srv);
 GSOFA_API int gsofa_serve_submit(gsofa_server* srv, const gsofa_csr* m, uint64_t* ticket);

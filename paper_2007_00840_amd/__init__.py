@@ -25,7 +25,7 @@ RESULT_ON_DEVICE = 0x4
 INPUT_ON_DEVICE = 0x8
 NO_LINE95 = 0x10
 LEVEL_ORDER = 0x20
-MAP_WAVE = 0x40
+MAP_WAVE32 = 0x40
 MAP_WG8 = 0x80
 MAP_WG16 = 0x100
 

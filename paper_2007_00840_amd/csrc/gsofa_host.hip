@@ -41,20 +41,39 @@ struct Status {
 };
 
 // ------------------------------------------------------ device memory cache
+//
+// Freed blocks stay cached for later calls. A block is freed while work on its
+// stream may still read or write it, so the release records an event on that
+// stream and the block is handed out again only on the same stream (stream
+// order protects it) or once the event has completed. Engine calls run on one
+// stream per thread; t_stream names it.
+
+thread_local hipStream_t t_stream = nullptr;
+
+struct StreamScope {
+    hipStream_t prev;
+    explicit StreamScope(hipStream_t s) : prev(t_stream) { t_stream = s; }
+    ~StreamScope() { t_stream = prev; }
+};
+
+void drop_idle_slots();
 
 class DevCache {
    public:
-    void* alloc(size_t bytes) {
+    void* alloc(size_t bytes, hipStream_t st) {
         if (bytes == 0) bytes = 256;
         bytes = (bytes + 255) & ~size_t(255);
         {
             std::lock_guard<std::mutex> g(mu_);
-            auto it = free_.lower_bound(bytes);
-            if (it != free_.end() && it->first <= bytes * 2 + (64ull << 20)) {
-                void* p = it->second;
-                size_t sz = it->first;
+            const size_t limit = bytes * 2 + (64ull << 20);
+            for (auto it = free_.lower_bound(bytes); it != free_.end() && it->first <= limit; ++it) {
+                Blk& b = it->second;
+                const bool ready = b.ev == nullptr || b.st == st || hipEventQuery(b.ev) == hipSuccess;
+                if (!ready) continue;
+                void* p = b.p;
+                if (b.ev) (void)hipEventDestroy(b.ev);
+                used_[p] = it->first;
                 free_.erase(it);
-                used_[p] = sz;
                 return p;
             }
         }
@@ -62,6 +81,7 @@ class DevCache {
         hipError_t e = hipMalloc(&p, bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
+            drop_idle_slots();
             release();
             e = hipMalloc(&p, bytes);
             if (e != hipSuccess) {
@@ -73,23 +93,50 @@ class DevCache {
         used_[p] = bytes;
         return p;
     }
-    void free(void* p) {
+    // synced: no work on the block can still be pending
+    void free(void* p, hipStream_t st, bool synced) {
         if (!p) return;
+        hipEvent_t ev = nullptr;
+        if (!synced) {
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+                hipEventRecord(ev, st) != hipSuccess) {
+                (void)hipGetLastError();
+                if (ev) (void)hipEventDestroy(ev);
+                ev = nullptr;
+                (void)hipStreamSynchronize(st);
+                (void)hipGetLastError();
+            }
+        }
         std::lock_guard<std::mutex> g(mu_);
         auto it = used_.find(p);
-        if (it == used_.end()) return;
-        free_.emplace(it->second, p);
+        if (it == used_.end()) {
+            if (ev) (void)hipEventDestroy(ev);
+            return;
+        }
+        free_.emplace(it->second, Blk{p, st, ev});
         used_.erase(it);
     }
     void release() {
         std::lock_guard<std::mutex> g(mu_);
-        for (auto& kv : free_) (void)hipFree(kv.second);
+        for (auto& kv : free_) {
+            if (kv.second.ev) {
+                (void)hipEventSynchronize(kv.second.ev);
+                (void)hipEventDestroy(kv.second.ev);
+            }
+            (void)hipFree(kv.second.p);
+        }
         free_.clear();
+        (void)hipGetLastError();
     }
 
    private:
+    struct Blk {
+        void* p;
+        hipStream_t st;
+        hipEvent_t ev;  // completes when the last work on the block is done; null: idle
+    };
     std::mutex mu_;
-    std::multimap<size_t, void*> free_;
+    std::multimap<size_t, Blk> free_;
     std::unordered_map<void*, size_t> used_;
 };
 
@@ -98,27 +145,32 @@ DevCache& cache() {
     return *c;
 }
 
-// A device buffer taken from the cache, returned on destruction.
+// A device buffer taken from the cache on the calling thread's engine stream,
+// returned with that stream's ordering on destruction.
 struct DBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    hipStream_t st = nullptr;
+    bool synced = false;  // set once no work on the buffer can be pending
     DBuf() = default;
-    explicit DBuf(size_t b) : p(cache().alloc(b)), bytes(b) {}
+    explicit DBuf(size_t b) : p(cache().alloc(b, t_stream)), bytes(b), st(t_stream) {}
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
-    DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; }
+    DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes), st(o.st), synced(o.synced) { o.p = nullptr; }
     DBuf& operator=(DBuf&& o) noexcept {
         if (this != &o) {
             reset();
             p = o.p;
             bytes = o.bytes;
+            st = o.st;
+            synced = o.synced;
             o.p = nullptr;
         }
         return *this;
     }
     ~DBuf() { reset(); }
     void reset() {
-        if (p) cache().free(p);
+        if (p) cache().free(p, st, synced);
         p = nullptr;
     }
     template <typename T>
@@ -126,12 +178,13 @@ struct DBuf {
 };
 
 // Slot state is kept initialised between calls: every source leaves its
-// bitmaps clear and its labels in a used-up range, so a later call with the
-// same layout can start at once.
+// pending bitmap clear and its labels in a used-up range, so a later call with
+// the same layout can start at once.
 struct SlotSet {
     DBuf buf;
     SlotLayout lay{};
     int32_t nslots = 0;
+    int mode = 0;  // 0: 32-bit labels, 1: byte states
 };
 
 std::mutex g_slot_mu;
@@ -140,7 +193,7 @@ std::vector<std::unique_ptr<SlotSet>>& idle_slots() {
     return *v;
 }
 
-std::unique_ptr<SlotSet> take_slots(const SlotLayout& lay, int32_t nslots, hipStream_t st) {
+std::unique_ptr<SlotSet> take_slots(const SlotLayout& lay, int32_t nslots, int mode, hipStream_t st) {
     {
         std::lock_guard<std::mutex> g(g_slot_mu);
         auto& v = idle_slots();
@@ -148,6 +201,11 @@ std::unique_ptr<SlotSet> take_slots(const SlotLayout& lay, int32_t nslots, hipSt
             if (v[i]->lay.N == lay.N && v[i]->nslots >= nslots) {
                 auto s = std::move(v[i]);
                 v.erase(v.begin() + i);
+                s->buf.st = st;
+                s->buf.synced = false;
+                // 32-bit labels left behind do not read as "not reached" bytes
+                if (s->mode != mode) chk(launch_init_slots(s->buf.as<uint8_t>(), s->nslots, s->lay, st));
+                s->mode = mode;
                 return s;
             }
         }
@@ -156,21 +214,31 @@ std::unique_ptr<SlotSet> take_slots(const SlotLayout& lay, int32_t nslots, hipSt
     s->buf = DBuf((size_t)lay.bytes_per_slot * nslots);
     s->lay = lay;
     s->nslots = nslots;
+    s->mode = mode;
     chk(launch_init_slots(s->buf.as<uint8_t>(), nslots, lay, st));
     return s;
 }
 
+// Called once the traversal that used the slots has completed.
 void give_slots(std::unique_ptr<SlotSet> s) {
-    std::lock_guard<std::mutex> g(g_slot_mu);
-    auto& v = idle_slots();
-    v.push_back(std::move(s));
-    // keep the cache bounded: at most 4 idle sets
-    while (v.size() > 4) v.erase(v.begin());
+    s->buf.synced = true;
+    std::vector<std::unique_ptr<SlotSet>> drop;
+    {
+        std::lock_guard<std::mutex> g(g_slot_mu);
+        auto& v = idle_slots();
+        v.push_back(std::move(s));
+        // keep the cache bounded: at most 4 idle sets
+        while (v.size() > 4) {
+            drop.push_back(std::move(v.front()));
+            v.erase(v.begin());
+        }
+    }
 }
 
 void drop_idle_slots() {
+    std::vector<std::unique_ptr<SlotSet>> drop;
     std::lock_guard<std::mutex> g(g_slot_mu);
-    idle_slots().clear();
+    drop.swap(idle_slots());
 }
 
 struct DeviceInfo {
@@ -255,11 +323,15 @@ struct Plan {
 // frontiers are small (a window holds a few dozen vertices), so a workgroup per
 // source leaves most of its wavefronts idle and was 3-5x slower on the 64^3
 // and 1000^2 stencils. The workgroup variants stay available as tuning knobs.
-int choose_mapping(uint32_t flags, int64_t N) {
-    (void)N;
+// Byte states (mapping 3) need windows of at most 253 ids and keep no label
+// for vertices already in the structure, so the paper's order (window = n) and
+// the line-9.5-off ablation run on 32-bit labels (mapping 0).
+int choose_mapping(uint32_t flags, int32_t window) {
     if (flags & GSOFA_MAP_WG16) return 1;
     if (flags & GSOFA_MAP_WG8) return 2;
-    return 0;
+    if (flags & GSOFA_MAP_WAVE32) return 0;
+    if (window > 253 || (flags & (GSOFA_NO_LINE95 | GSOFA_LEVEL_ORDER))) return 0;
+    return 3;
 }
 
 int32_t auto_window(int64_t N) {
@@ -277,6 +349,22 @@ struct EngineOut {
 
 // Per-launch fill-ratio memory used to size the output pool of later calls.
 std::atomic<double> g_fill_ratio{48.0};
+
+// Device bytes a launch needs besides slots and output pool: inputs, per-row
+// arrays, assembly buffers, scratch.
+int64_t fixed_bytes(int64_t nrows, int64_t nnz) { return nrows * 40 + nnz * 8 + (64ll << 20); }
+
+// Output-pool entries expected for nnz stored entries.
+int64_t pool_estimate(int64_t nrows, int64_t nnz) {
+    return std::max<int64_t>((int64_t)(g_fill_ratio.load() * (double)nnz * 1.15) + nrows, 1 << 20);
+}
+
+// Budget under which the planner below gives nslots slots and the expected
+// pool: half of the room after fixed_bytes goes to slots, and the pool may
+// take up to a third of the rest in 4-byte entries.
+int64_t budget_for(int64_t nrows, int64_t nnz, int64_t nslots, const SlotLayout& lay) {
+    return fixed_bytes(nrows, nnz) + 2 * nslots * lay.bytes_per_slot + 12 * pool_estimate(nrows, nnz);
+}
 
 __global__ void k_rebase_ptr(int32_t njobs, const int64_t* job_row_base, const int32_t* job_n,
                              const int64_t* g, int64_t* out) {
@@ -302,6 +390,7 @@ struct Engine {
 
     int run() {
         const double t0 = now_ms();
+        StreamScope scope(st);
         const int32_t nj = (int32_t)mats.size();
         results.assign(nj, nullptr);
         std::vector<int> jstat(nj, GSOFA_OK);
@@ -402,23 +491,22 @@ struct Engine {
         const SlotLayout lay = slot_layout(N);
         const DeviceInfo di = device_info();
         int64_t budget = plan.budget > 0 ? plan.budget : (int64_t)(di.free_b * 0.9);
-        const int64_t fixed = (int64_t)(nrows * 40 + total_nnz * 8) + (64ll << 20);
+        const int64_t fixed = fixed_bytes(nrows, total_nnz);
         if (budget < fixed + lay.bytes_per_slot) throw Status{GSOFA_ENOMEM};
-        const int mapping = choose_mapping(plan.flags, N);
+        const int mapping = choose_mapping(plan.flags, plan.window);
         int64_t want = plan.nslots > 0 ? plan.nslots : (int64_t)traverse_resident_slots(di.cus, mapping);
         want = std::min<int64_t>(want, std::max<int64_t>(items, 1));
         const int64_t slot_room = (budget - fixed) / 2;  // half of the rest for slots
         int64_t nslots = std::min<int64_t>(want, std::max<int64_t>(slot_room / lay.bytes_per_slot, 1));
         nslots = std::max<int64_t>(nslots, 1);
         // the one-wavefront mapping launches whole blocks of 4 wavefronts
-        if (mapping == 0 && nslots > 4) nslots = nslots / 4 * 4;
+        if ((mapping == 0 || mapping == 3) && nslots > 4) nslots = nslots / 4 * 4;
 
-        int64_t pool_cap = std::max<int64_t>((int64_t)(g_fill_ratio.load() * (double)total_nnz * 1.15) + nrows,
-                                             1 << 20);
+        int64_t pool_cap = pool_estimate(nrows, total_nnz);
         const int64_t pool_room = (budget - fixed - nslots * lay.bytes_per_slot) / 4 / 3;
         pool_cap = std::max<int64_t>(std::min<int64_t>(pool_cap, pool_room), nrows + 1024);
 
-        auto slots = take_slots(lay, (int32_t)nslots, st);
+        auto slots = take_slots(lay, (int32_t)nslots, mapping == 3 ? 1 : 0, st);
 
         DBuf row_off(8 * (size_t)std::max<int64_t>(nrows, 1));
         DBuf row_cnt(4 * (size_t)std::max<int64_t>(nrows, 1));
@@ -748,6 +836,9 @@ struct Engine {
         }
         chk(hipStreamSynchronize(st));
         if (dev_out) {
+            for (DBuf* b : {&u_idx, &u_ptr, &l_rptr, &l_ridx, &l_cptr, &l_cidx, &xsup_all, &supno_all,
+                            &u_ptr_loc, &l_ptr_loc})
+                b->synced = true;
             keep->push_back(std::move(u_idx));
             keep->push_back(std::move(u_ptr));
             if (l_csr) {
@@ -994,8 +1085,7 @@ namespace {
 
 int64_t estimate_request_bytes(int32_t n, int64_t nnz, int32_t nslots) {
     const SlotLayout lay = slot_layout(std::max<int64_t>(n, 1));
-    const double ratio = std::max(8.0, g_fill_ratio.load());
-    return lay.bytes_per_slot * nslots + (int64_t)(nnz * ratio * 4 * 3.5) + (int64_t)n * 120 + (32ll << 20);
+    return budget_for(n, nnz, nslots, lay);
 }
 
 int32_t serve_slots_for(const gsofa_server* s, int32_t n) {
@@ -1052,7 +1142,7 @@ extern "C" GSOFA_API int gsofa_serve_open(const gsofa_opts* opts, int32_t max_in
     try {
         (void)hipGetDevice(&s->device);
         DeviceInfo di = device_info();
-        s->slots_total = traverse_resident_slots(di.cus, 0);
+        s->slots_total = traverse_resident_slots(di.cus, 3);
         s->budget = s->opts.mem_budget_bytes > 0 ? s->opts.mem_budget_bytes : (int64_t)(di.free_b * 0.85);
         s->streams.assign(s->max_inflight, nullptr);
         for (auto& st : s->streams) chk(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -1119,8 +1209,11 @@ extern "C" GSOFA_API int gsofa_serve_poll(gsofa_server* s, uint64_t ticket, int3
 extern "C" GSOFA_API int gsofa_serve_close(gsofa_server* s) {
     if (!s) return GSOFA_EINVAL;
     {
+        // requests not admitted yet are dropped; running ones finish
         std::lock_guard<std::mutex> g(s->mu);
         s->closing = true;
+        for (auto& r : s->queue) s->known.erase(r.ticket);
+        s->queue.clear();
         s->cv.notify_all();
     }
     for (auto& t : s->workers)

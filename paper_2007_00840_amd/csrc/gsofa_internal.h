@@ -39,7 +39,7 @@ struct SlotLayout {
     int64_t N;
     int64_t nw64;             // 64-bit words of the pending bitmap
     int64_t qcap;             // worklist capacity
-    int64_t off_lab, off_p, off_qs, off_qa, off_qb, off_row, off_meta;
+    int64_t off_lab, off_p, off_qs, off_qa, off_qb, off_row, off_touch, off_meta;
     int64_t bytes_per_slot;
 };
 
@@ -64,7 +64,8 @@ struct TraverseArgs {
     JobStats* jstats;
     int32_t window;                   // threshold-window span in vertex ids
     uint32_t flags;
-    int32_t mapping;                  // 0: one wavefront per source; 1: 16, 2: 8 wavefronts
+    int32_t mapping;                  // 0: one wavefront per source (32-bit labels); 1: 16, 2: 8
+                                      // wavefronts per source; 3: one wavefront, byte states
 };
 
 // Row-space description shared by the assembly kernels. With one job,

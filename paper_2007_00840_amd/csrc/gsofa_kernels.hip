@@ -137,6 +137,7 @@ SlotLayout slot_layout(int64_t N) {
     L.off_qa = take(4 * L.qcap);
     L.off_qb = take(4 * L.qcap);
     L.off_row = take(4 * N);
+    L.off_touch = take(4 * N);
     L.bytes_per_slot = o;
     return L;
 }
@@ -613,6 +614,422 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
     }
 }
 
+// ------------------------------------------------- byte-state variant
+//
+// Inside a window a label only ever takes values in [lo, hi), and once the
+// window is over a vertex is final: in the structure or not. So one byte per
+// vertex is enough for windows of up to 253 ids:
+//   0        in the structure (passes its own id on)
+//   1 .. D   reached in the current window, label lo + byte - 1
+//   0xFE     reached in an earlier window, not in the structure (final)
+//   0xFF     not reached by this source
+// A quarter of the 32-bit label footprint keeps more of each source's state in
+// L2. Bytes change by compare-and-swap on their 32-bit word. Reached vertices
+// are listed and their bytes reset to 0xFF when the source is done.
+constexpr uint32_t kStStruct = 0u, kStSettled = 0xFEu, kStNone = 0xFFu;
+
+__global__ __launch_bounds__(256) void k_traverse8(TraverseArgs a) {
+    __shared__ WaveTile tiles[kTravWaves];
+    __shared__ unsigned long long pushed[kTravWaves][1 << kHashBits];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ln = lane_id();
+    const int32_t slot = blockIdx.x * kTravWaves + wv;
+    if (slot >= a.nslots) return;
+    WaveTile& T = tiles[wv];
+    unsigned long long* H = pushed[wv];
+
+    uint8_t* sb = a.slots + (int64_t)slot * a.lay.bytes_per_slot;
+    GLOBAL uint8_t* st8 = gbl((uint8_t*)(sb + a.lay.off_lab));
+    GLOBAL uint32_t* stw = gbl((uint32_t*)(sb + a.lay.off_lab));
+    GLOBAL unsigned long long* P = gbl((unsigned long long*)(sb + a.lay.off_p));
+    GLOBAL int32_t* qa = gbl((int32_t*)(sb + a.lay.off_qa));
+    GLOBAL int32_t* qb = gbl((int32_t*)(sb + a.lay.off_qb));
+    GLOBAL int32_t* rowb = gbl((int32_t*)(sb + a.lay.off_row));
+    GLOBAL int32_t* touch = gbl((int32_t*)(sb + a.lay.off_touch));
+    GLOBAL uint32_t* qs = gbl((uint32_t*)(sb + a.lay.off_qs));
+    GLOBAL uint32_t* meta = gbl((uint32_t*)(sb + a.lay.off_meta));
+    const __amdgpu_buffer_rsrc_t st_r =
+        __builtin_amdgcn_make_buffer_rsrc((uint8_t*)(sb + a.lay.off_lab), (short)0, (int)a.lay.N, 0x00020000);
+
+    const uint32_t R = (uint32_t)a.lay.N;
+    uint32_t lvl = meta[1];
+    const int32_t D = a.window;  // 1 .. 253
+    for (int i = ln; i < (1 << kHashBits); i += 64) H[i] = ~0ull;
+
+
+    for (;;) {
+        unsigned long long k = 0;
+        if (ln == 0) k = atomicAdd(a.item_counter, 1ull);
+        k = __shfl(k, 0, 64);
+        if (k >= (unsigned long long)a.nitems) break;
+
+        int32_t j, s;
+        if (a.item_rows) {
+            const int64_t gr = a.item_rows[k];
+            j = a.row_job ? a.row_job[gr] : 0;
+            s = (int32_t)(gr - a.jobs[j].row_base);
+        } else {
+            int32_t lo = 0, hi = a.njobs - 1;
+            while (lo < hi) {
+                int32_t mid = (lo + hi + 1) >> 1;
+                if (a.jobs[mid].item_base <= (int64_t)k) lo = mid;
+                else hi = mid - 1;
+            }
+            j = lo;
+            s = a.jobs[j].n - 1 - (int32_t)((int64_t)k - a.jobs[j].item_base);
+        }
+        j = __builtin_amdgcn_readfirstlane(j);
+        s = __builtin_amdgcn_readfirstlane(s);
+        const GLOBAL int32_t* rp = gbl(a.jobs[j].row_ptr);
+        const GLOBAL int32_t* ci = gbl(a.jobs[j].col_idx);
+        const int64_t grow = a.jobs[j].row_base + s;
+        if (lvl >= 0xF0000000u) {
+            for (int i = ln; i < (1 << kHashBits); i += 64) H[i] = ~0ull;
+            for (int64_t i = ln; i < (int64_t)R; i += 64) qs[i] = 0u;
+            lvl = 0;
+            slot_fence();
+        }
+
+        unsigned long long e_alg = 0, e_gpu = 0;
+        int32_t rcount = 0, lcount = 0, tcount = 0;
+        uint32_t n_iter = 0, n_win = 0;
+
+        // ---- seed: original entries of row s enter the structure
+        const int32_t rs = rp[s], re = rp[s + 1];
+        int32_t ndiag = 0;
+        bool dup = false;
+        int32_t pmin = 0x7FFFFFFF;
+        for (int32_t e0 = rs; e0 < re; e0 += 64) {
+            const int32_t e = e0 + ln;
+            const bool act = e < re;
+            const int32_t w = act ? ci[e] : -1;
+            ndiag += __popcll(__ballot(act && w == s));
+            bool fresh = false;
+            if (act && w != s) {
+                const uint32_t sh = (uint32_t)(w & 3) * 8u;
+                const uint32_t old = wg_and(&stw[w >> 2], ~(0xFFu << sh));  // byte -> 0
+                fresh = ((old >> sh) & 0xFFu) == kStNone;
+                dup |= !fresh;
+            }
+            const bool below = fresh && w < s;
+            {
+                unsigned long long m = __ballot(fresh);
+                if (fresh) rowb[rcount + (int32_t)lanes_below(m)] = w;
+                rcount += __popcll(m);
+            }
+            lcount += __popcll(__ballot(below));
+            if (below) {
+                wg_or(&P[w >> 6], 1ull << (w & 63));
+                e_alg += (unsigned long long)(rp[w + 1] - rp[w]);
+                pmin = min(pmin, w);
+            }
+        }
+        if (ln == 0) {
+            e_alg += (unsigned long long)(re - rs);
+            e_gpu += (unsigned long long)(re - rs);
+        }
+        if (__ballot(dup) != 0ull || ndiag > 1) {
+            if (ln == 0) atomicOr(&a.jstats[j].err, kErrDuplicate);
+        }
+        pmin = wave_min(pmin);
+        slot_fence();
+
+        // ---- windows of increasing keys
+        const int32_t nwp = (s + 63) >> 6;
+        int32_t pos = pmin;
+        while (pos < s) {
+            int32_t found = -1;
+            for (int32_t w0 = pos >> 6; w0 < nwp; w0 += 64) {
+                const int32_t wi = w0 + ln;
+                const unsigned long long word = (wi < nwp) ? ld_coherent(&P[wi]) : 0ull;
+                const unsigned long long nz = __ballot(word != 0ull);
+                if (nz) {
+                    const int jl = __builtin_ctzll(nz);
+                    const unsigned long long wd = __shfl(word, jl, 64);
+                    found = (w0 + jl) * 64 + __builtin_ctzll(wd);
+                    break;
+                }
+            }
+            if (found < 0) break;
+            const int32_t lo = found;
+            const int32_t hi = (int32_t)min((int64_t)lo + D, (int64_t)s);
+            ++n_win;
+
+            GLOBAL int32_t* cur = qa;
+            GLOBAL int32_t* nxt = qb;
+            int32_t qn = 0;
+            const int32_t wlast = (hi - 1) >> 6;
+            for (int32_t w0 = lo >> 6; w0 <= wlast; w0 += 64) {
+                const int32_t wi = w0 + ln;
+                unsigned long long word = 0ull;
+                if (wi <= wlast) {
+                    word = ld_coherent(&P[wi]);
+                    const int64_t b0 = (int64_t)wi * 64;
+                    unsigned long long m = ~0ull;
+                    if (b0 < lo) m &= ~0ull << (lo - b0);
+                    if (b0 + 64 > hi) m &= (hi - b0 >= 64) ? ~0ull : ((1ull << (hi - b0)) - 1ull);
+                    word &= m;
+                    if (word) wg_and(&P[wi], ~word);
+                }
+                const int c = __popcll(word);
+                const int incl = wave_incl_scan(c);
+                int32_t o = qn + incl - c;
+                while (word) {
+                    const int b = __builtin_ctzll(word);
+                    word &= word - 1ull;
+                    cur[o++] = wi * 64 + b;
+                }
+                qn += __shfl(incl, 63, 64);
+            }
+            const int32_t tmark = tcount;
+            wave_fence();
+
+            while (qn > 0) {
+                ++lvl;
+                ++n_iter;
+                int32_t nq = 0;
+                bool exact = false;
+                for (int32_t c0 = 0; c0 < qn; c0 += 64) {
+                    const int32_t i = c0 + ln;
+                    const bool act = i < qn;
+                    const int32_t f = ld_coherent(&cur[act ? i : 0]);
+                    const int32_t fs = rp[f];
+                    const int32_t deg = act ? rp[f + 1] - fs : 0;
+                    const uint32_t fb = (ld_coherent(&stw[f >> 2]) >> ((f & 3) * 8)) & 0xFFu;
+                    // a frontier is in the structure (passes its id) or reached in this window
+                    const uint32_t ov = fb == kStStruct ? (uint32_t)f
+                                                        : (fb >= 1u && fb <= (uint32_t)D) ? (uint32_t)lo + fb - 1u : kInf;
+                    e_gpu += (unsigned long long)deg;
+                    const int32_t incl = wave_incl_scan(deg);
+                    const int32_t total = __shfl(incl, 63, 64);
+                    auto round = [&](int32_t (&widx)[kIlp], uint32_t (&outv)[kIlp], bool (&act_e)[kIlp]) {
+                        int32_t w[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) w[kk] = ci[widx[kk]];
+                        uint32_t sb8[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            act_e[kk] = act_e[kk] && w[kk] != s && outv[kk] != kInf;
+                            const uint32_t off = act_e[kk] ? (uint32_t)w[kk] : 0xFFFFFFF0u;
+                            sb8[kk] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(st_r, off, 0, 0);
+                        }
+                        // candidates: an unseen U vertex, or a label the edge lowers
+                        bool cand[kIlp];
+                        uint32_t nb[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            const uint32_t b = sb8[kk];
+                            const uint32_t olab = b == kStNone ? kInf
+                                                  : (b == kStStruct || b == kStSettled) ? 0u : (uint32_t)lo + b - 1u;
+                            if (w[kk] > s) {
+                                cand[kk] = act_e[kk] && b == kStNone;
+                                nb[kk] = kStStruct;
+                            } else {
+                                cand[kk] = act_e[kk] && b != kStStruct && b != kStSettled && outv[kk] < olab;
+                                nb[kk] = outv[kk] < (uint32_t)w[kk] ? kStStruct : outv[kk] - (uint32_t)lo + 1u;
+                            }
+                        }
+                        // byte updates: compare-and-swap on the containing word
+                        uint32_t ob[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            ob[kk] = 0x100u;  // no change
+                            if (!cand[kk]) continue;
+                            const int32_t wk = w[kk];
+                            GLOBAL uint32_t* word = &stw[wk >> 2];
+                            const uint32_t sh = (uint32_t)(wk & 3) * 8u;
+                            uint32_t cw = *word;
+                            for (;;) {
+                                const uint32_t b = (cw >> sh) & 0xFFu;
+                                bool improves;
+                                if (wk > s) improves = b == kStNone;
+                                else {
+                                    const uint32_t olab = b == kStNone ? kInf
+                                                          : (b == kStStruct || b == kStSettled) ? 0u
+                                                                                                : (uint32_t)lo + b - 1u;
+                                    improves = b != kStStruct && b != kStSettled && outv[kk] < olab;
+                                }
+                                if (!improves) break;
+                                const uint32_t nw = (cw & ~(0xFFu << sh)) | (nb[kk] << sh);
+                                if (__hip_atomic_compare_exchange_strong(word, &cw, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                                         __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                                    ob[kk] = b;
+                                    break;
+                                }
+                            }
+                        }
+                        bool emit[kIlp], isl[kIlp], push[kIlp], first[kIlp], tch[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            const int32_t wk = w[kk];
+                            const bool chg = ob[kk] != 0x100u;
+                            emit[kk] = isl[kk] = push[kk] = tch[kk] = false;
+                            first[kk] = chg && wk < s && ob[kk] == kStNone;
+                            if (!chg) continue;
+                            if (wk > s) {
+                                emit[kk] = true;
+                                continue;
+                            }
+                            if (nb[kk] == kStStruct) {
+                                // label fell below w: fill (s, w)
+                                emit[kk] = true;
+                                isl[kk] = true;
+                                if (wk < hi) push[kk] = true;
+                                else wg_or(&P[wk >> 6], 1ull << (wk & 63));
+                            } else {
+                                push[kk] = true;
+                                tch[kk] = ob[kk] == kStNone;
+                            }
+                        }
+                        int32_t fdeg[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk)
+                            fdeg[kk] = first[kk] ? rp[w[kk] + 1] - rp[w[kk]] : 0;
+                        bool evict = false;
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            if (push[kk]) {
+                                const unsigned long long key = ((unsigned long long)lvl << 32) | (uint32_t)w[kk];
+                                const uint32_t h = ((uint32_t)w[kk] * 2654435761u) >> (32 - kHashBits);
+                                const unsigned long long prev = __hip_atomic_exchange(
+                                    &H[h], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                                push[kk] = prev != key;
+                                evict |= push[kk] && (uint32_t)(prev >> 32) == lvl;
+                            }
+                        }
+                        if (exact) {
+#pragma unroll
+                            for (int kk = 0; kk < kIlp; ++kk)
+                                if (push[kk]) push[kk] = wg_xchg(&qs[w[kk]], lvl) != lvl;
+                        }
+                        exact = exact || __ballot(evict) != 0ull;
+                        bool any = false;
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            e_alg += (unsigned long long)fdeg[kk];
+                            any |= emit[kk] | push[kk] | tch[kk];
+                        }
+                        if (__ballot(any) == 0ull) return;
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            unsigned long long m = __ballot(emit[kk]);
+                            if (emit[kk]) rowb[rcount + (int32_t)lanes_below(m)] = w[kk];
+                            rcount += __popcll(m);
+                            lcount += __popcll(__ballot(isl[kk]));
+                            m = __ballot(push[kk]);
+                            if (push[kk]) nxt[nq + (int32_t)lanes_below(m)] = w[kk];
+                            nq += __popcll(m);
+                            m = __ballot(tch[kk]);
+                            if (tch[kk]) touch[tcount + (int32_t)lanes_below(m)] = w[kk];
+                            tcount += __popcll(m);
+                        }
+                    };
+                    const int32_t maxdeg = wave_max(deg);
+                    if (maxdeg <= 64) {
+                        for (int32_t t0 = 0; t0 < maxdeg; t0 += kIlp) {
+                            int32_t widx[kIlp];
+                            uint32_t outv[kIlp];
+                            bool act_e[kIlp];
+#pragma unroll
+                            for (int kk = 0; kk < kIlp; ++kk) {
+                                act_e[kk] = t0 + kk < deg;
+                                widx[kk] = act_e[kk] ? fs + t0 + kk : 0;
+                                outv[kk] = ov;
+                            }
+                            round(widx, outv, act_e);
+                        }
+                    } else {
+                        T.scan[ln] = incl;
+                        T.start[ln] = fs;
+                        T.outv[ln] = ov;
+                        wave_fence();
+                        for (int32_t r0 = 0; r0 < total; r0 += 64 * kIlp) {
+                            int32_t widx[kIlp];
+                            uint32_t outv[kIlp];
+                            bool act_e[kIlp];
+#pragma unroll
+                            for (int kk = 0; kk < kIlp; ++kk) {
+                                const int32_t ei = r0 + kk * 64 + ln;
+                                int32_t jl = 0, jh = 63;
+                                while (jl < jh) {
+                                    const int32_t mid = (jl + jh) >> 1;
+                                    if (T.scan[mid] > ei) jh = mid;
+                                    else jl = mid + 1;
+                                }
+                                const int32_t excl = jl ? T.scan[jl - 1] : 0;
+                                act_e[kk] = ei < total;
+                                widx[kk] = act_e[kk] ? T.start[jl] + (ei - excl) : 0;
+                                outv[kk] = T.outv[jl];
+                            }
+                            round(widx, outv, act_e);
+                        }
+                    }
+                    wave_fence();
+                }
+                GLOBAL int32_t* t = cur;
+                cur = nxt;
+                nxt = t;
+                qn = nq;
+                wave_fence();
+            }
+            // the window is over: everything it reached outside the structure is final
+            for (int32_t i = tmark + ln; i < tcount; i += 64) {
+                const int32_t v = ld_coherent(&touch[i]);
+                const uint32_t sh = (uint32_t)(v & 3) * 8u;
+                uint32_t cw = ld_coherent(&stw[v >> 2]);
+                for (;;) {
+                    const uint32_t b = (cw >> sh) & 0xFFu;
+                    if (b == kStStruct || b == kStSettled) break;
+                    const uint32_t nw = (cw & ~(0xFFu << sh)) | (kStSettled << sh);
+                    if (__hip_atomic_compare_exchange_strong(&stw[v >> 2], &cw, nw, __ATOMIC_RELAXED,
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                        break;
+                }
+            }
+            wave_fence();
+            pos = hi;
+        }
+
+        // ---- finish the row: diagonal, copy to the pool, reset the state bytes
+        if (ln == 0) rowb[rcount] = s;
+        rcount += 1;
+        slot_fence();
+        unsigned long long off = 0;
+        if (ln == 0) off = atomicAdd(a.pool_tail, (unsigned long long)rcount);
+        off = __shfl(off, 0, 64);
+        const bool fits = (int64_t)(off + rcount) <= a.pool_cap;
+        GLOBAL int32_t* pool = gbl(a.pool);
+        if (fits)
+            for (int32_t i = ln; i < rcount; i += 64) pool[off + i] = ld_coherent(&rowb[i]);
+        if (ln == 0) {
+            a.row_off[grow] = fits ? (int64_t)off : -1;
+            a.row_cnt[grow] = rcount;
+            a.row_lcnt[grow] = lcount;
+            if (!fits) atomicOr(&a.jstats[j].err, kErrOverflow);
+        }
+        for (int32_t i = ln; i < rcount - 1; i += 64) {
+            const int32_t v = ld_coherent(&rowb[i]);
+            wg_or(&stw[v >> 2], 0xFFu << ((v & 3) * 8));
+        }
+        for (int32_t i = ln; i < tcount; i += 64) {
+            const int32_t v = ld_coherent(&touch[i]);
+            wg_or(&stw[v >> 2], 0xFFu << ((v & 3) * 8));
+        }
+
+        e_alg = wave_sum_u64(e_alg);
+        e_gpu = wave_sum_u64(e_gpu);
+        if (ln == 0) {
+            atomicAdd(&a.jstats[j].edges_alg, e_alg);
+            atomicAdd(&a.jstats[j].edges_gpu, e_gpu);
+            atomicAdd(&a.jstats[j].iterations, (unsigned long long)n_iter);
+            atomicAdd(&a.jstats[j].windows, (unsigned long long)n_win);
+            if (ndiag > 0) atomicAdd(&a.jstats[j].diag, 1ull);
+        }
+        slot_fence();
+    }
+    if (ln == 0) meta[1] = lvl;
+}
+
 // --------------------------------------------- workgroup-per-source variant
 //
 // The same traversal with NW wavefronts cooperating on one source: fewer
@@ -1013,14 +1430,15 @@ __global__ __launch_bounds__(64 * NW) void k_traverse_wg(TraverseArgs a) {
 int32_t traverse_resident_slots(int cus, int mapping) {
     int blocks = 0;
     hipError_t e;
-    if (mapping == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse_wg<16>, 64 * 16, 0);
+    if (mapping == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse8, 64 * kTravWaves, 0);
+    else if (mapping == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse_wg<16>, 64 * 16, 0);
     else if (mapping == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse_wg<8>, 64 * 8, 0);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse, 64 * kTravWaves, 0);
     if (e != hipSuccess || blocks <= 0) {
         (void)hipGetLastError();
         blocks = 1;
     }
-    return blocks * (mapping == 0 ? kTravWaves : 1) * cus;
+    return blocks * ((mapping == 0 || mapping == 3) ? kTravWaves : 1) * cus;
 }
 
 hipError_t launch_traverse(const TraverseArgs& a, hipStream_t st) {
@@ -1029,6 +1447,9 @@ hipError_t launch_traverse(const TraverseArgs& a, hipStream_t st) {
         hipLaunchKernelGGL(k_traverse_wg<16>, dim3(a.nslots), dim3(64 * 16), 0, st, a);
     } else if (a.mapping == 2) {
         hipLaunchKernelGGL(k_traverse_wg<8>, dim3(a.nslots), dim3(64 * 8), 0, st, a);
+    } else if (a.mapping == 3) {
+        const int blocks = (a.nslots + kTravWaves - 1) / kTravWaves;
+        hipLaunchKernelGGL(k_traverse8, dim3(blocks), dim3(64 * kTravWaves), 0, st, a);
     } else {
         const int blocks = (a.nslots + kTravWaves - 1) / kTravWaves;
         hipLaunchKernelGGL(k_traverse, dim3(blocks), dim3(64 * kTravWaves), 0, st, a);

@@ -158,6 +158,7 @@ def test_generator_families(g, idx):
     {"flags": 0x40}, {"flags": 0x80}, {"flags": 0x100}, {"flags": 0x100 | 0x20},
     {"flags": 0x80, "concurrent_sources": 3}, {"flags": 0x100, "window": 1},
     {"flags": 0x80 | 0x10, "window": 64},
+    {"window": 253}, {"window": 200, "concurrent_sources": 5}, {"window": 254},
 ], ids=str)
 def test_knobs_do_not_change_results(g, kw):
     m = synth.stencil(27, (11, 10, 9), nd=True, seed=21)
