@@ -173,6 +173,10 @@ def bench_serve(g, synth, cap_s):
     return out
 
 
+# traversal kernel launched for each mapping code reported in the stats
+KERNEL_OF_MAPPING = {3: "k_traverse8", 0: "k_traverse", 2: "k_traverse_wg<8>", 1: "k_traverse_wg<16>"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,7 +195,7 @@ def main():
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the symbolic engine runs on one GPU per process; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
@@ -217,11 +221,15 @@ def main():
     flags = g.RESULT_ON_DEVICE | args.flags
     kw = dict(flags=flags, window=args.window, concurrent_sources=args.slots, stream=stream)
 
+    warm_stats = []
     for i in range(args.warmup):
         t0 = time.perf_counter()
         r = g.symbolic(m.n, rp, ci, **kw)
+        warm_stats.append(r.stats)
         log(f"warmup {i}: {1e3 * (time.perf_counter() - t0):.1f} ms, "
-            f"traverse {r.stats['t_traverse_ms']:.1f} ms")
+            f"traverse {r.stats['t_traverse_ms']:.1f} ms, tuner {r.stats['t_tune_ms']:.1f} ms -> "
+            f"mapping {r.stats['mapping']} window {r.stats['window']} "
+            f"sources {r.stats['concurrent_sources']}")
         r.free()
     torch.cuda.synchronize()
     stats = []
@@ -271,7 +279,8 @@ def main():
                    "max_supernode": 128, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_traverse", "bytes_per_unit": BYTES_PER_EDGE,
+                     "kernel": KERNEL_OF_MAPPING.get(stats[-1]["mapping"], "k_traverse"),
+                     "bytes_per_unit": BYTES_PER_EDGE,
                      "unit_count": e_alg, "kernel_ms": round(t_trav, 3)},
         "cpu_baseline": base,
         "edges_alg": e_alg,
@@ -282,6 +291,8 @@ def main():
         "t_traverse_ms": round(t_trav, 3), "t_emit_ms": round(t_emit, 3),
         "t_supernode_ms": round(t_sn, 3),
         "concurrent_sources": stats[-1]["concurrent_sources"],
+        "window": stats[-1]["window"], "mapping": stats[-1]["mapping"],
+        "t_tune_ms_warmup": round(max(s["t_tune_ms"] for s in warm_stats), 3) if warm_stats else 0.0,
         "batch": batch,
         "serve": serve,
     }

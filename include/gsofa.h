@@ -79,6 +79,22 @@ typedef enum {
 #define GSOFA_MAP_WAVE32        0x40u  /* one wavefront per source row, 32-bit labels  */
 #define GSOFA_MAP_WG8           0x80u  /* eight wavefronts per source row              */
 #define GSOFA_MAP_WG16          0x100u /* sixteen wavefronts per source row            */
+/* By default the device work of a call between two host synchronisations
+ * (traversal; pointer scans; row sort; supernodes; L transpose and result
+ * pointers) is captured into HIP graphs and each phase is one graph launch;
+ * executable graphs are cached per phase and updated in place for the next
+ * call. GSOFA_EAGER launches every kernel on the stream instead; results are
+ * identical. */
+#define GSOFA_EAGER             0x200u
+/* With window = 0, concurrent_sources = 0 and no mapping or ablation flag, the
+ * window span, the mapping and the sources in flight are autotuned: for each
+ * size class (device, log2 of the largest n, mean row length, batch size) the
+ * first call with at least 65,536 source rows times every candidate on one
+ * stratified sample of its rows and keeps the fastest for later calls; smaller
+ * calls of an untuned class use window 16 with byte states. GSOFA_TUNE_NOW
+ * times the candidates in this call whatever its size, and re-tunes its class.
+ * Results are identical for every choice. */
+#define GSOFA_TUNE_NOW          0x400u
 
 /* A CSR pattern: n rows, row_ptr[n+1], col_idx[row_ptr[n]]; host pointers
  * unless GSOFA_INPUT_ON_DEVICE is set. */
@@ -102,6 +118,11 @@ typedef struct {
     double t_emit_ms;           /* pointer scans and per-row sort into CSR                */
     double t_supernode_ms;
     double t_total_ms;          /* whole call, host copies included                       */
+    int32_t window;             /* threshold-window span used                             */
+    int32_t mapping;            /* traversal mapping used: 3 one wavefront per source with
+                                   byte states, 0 the same with 32-bit labels, 2 / 1 eight /
+                                   sixteen wavefronts per source                          */
+    double t_tune_ms;           /* autotuner trial time spent in this call (0 if none)    */
 } gsofa_stats;
 
 typedef void* (*gsofa_alloc_fn)(size_t bytes, void* ctx);
@@ -198,6 +219,11 @@ GSOFA_API const char* gsofa_strerror(int status);
 
 /* Releases cached device memory held between calls on the current device. */
 GSOFA_API int gsofa_release_cache(void);
+
+/* Process-wide HIP graph counters since load: out[0] executable graphs
+ * instantiated, out[1] executable graphs updated in place for a later call,
+ * out[2] graph launches. out must hold 3 entries; GSOFA_EINVAL if NULL. */
+GSOFA_API int gsofa_graph_counters(uint64_t* out);
 
 #ifdef __cplusplus
 }

@@ -28,10 +28,12 @@ LEVEL_ORDER = 0x20
 MAP_WAVE32 = 0x40
 MAP_WG8 = 0x80
 MAP_WG16 = 0x100
+EAGER = 0x200
+TUNE_NOW = 0x400
 
 EXPORTED = ["gsofa_symbolic", "gsofa_batch", "gsofa_serve_open", "gsofa_serve_submit",
             "gsofa_serve_poll", "gsofa_serve_close", "gsofa_result_free", "gsofa_strerror",
-            "gsofa_release_cache"]
+            "gsofa_release_cache", "gsofa_graph_counters"]
 
 
 class GsofaError(RuntimeError):
@@ -50,7 +52,8 @@ class Stats(ctypes.Structure):
                 ("edges_alg", ctypes.c_uint64), ("edges_gpu", ctypes.c_uint64),
                 ("peak_device_bytes", ctypes.c_uint64), ("t_traverse_ms", ctypes.c_double),
                 ("t_emit_ms", ctypes.c_double), ("t_supernode_ms", ctypes.c_double),
-                ("t_total_ms", ctypes.c_double)]
+                ("t_total_ms", ctypes.c_double), ("window", ctypes.c_int32),
+                ("mapping", ctypes.c_int32), ("t_tune_ms", ctypes.c_double)]
 
 
 class Opts(ctypes.Structure):
@@ -102,6 +105,8 @@ def load():
         lib.gsofa_strerror.argtypes = [ctypes.c_int]
         lib.gsofa_release_cache.restype = ctypes.c_int
         lib.gsofa_release_cache.argtypes = []
+        lib.gsofa_graph_counters.restype = ctypes.c_int
+        lib.gsofa_graph_counters.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
         _lib = lib
     return _lib
 
@@ -367,3 +372,12 @@ class Server:
 
 def release_cache():
     return load().gsofa_release_cache()
+
+
+def graph_counters():
+    """(instantiated, updated in place, launched) executable HIP graphs since load."""
+    out = (ctypes.c_uint64 * 3)()
+    rc = load().gsofa_graph_counters(out)
+    if rc != OK:
+        raise GsofaError(rc, "gsofa_graph_counters")
+    return tuple(int(x) for x in out)

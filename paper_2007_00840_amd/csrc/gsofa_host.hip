@@ -14,6 +14,7 @@
 #include <mutex>
 #include <new>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -177,6 +178,179 @@ struct DBuf {
     T* as() const { return static_cast<T*>(p); }
 };
 
+// Pinned host memory for small device-to-host reads inside a call.
+struct PinnedBuf {
+    void* p = nullptr;
+    explicit PinnedBuf(size_t b) { chk(hipHostMalloc(&p, std::max<size_t>(b, 8), hipHostMallocDefault)); }
+    PinnedBuf(const PinnedBuf&) = delete;
+    PinnedBuf& operator=(const PinnedBuf&) = delete;
+    ~PinnedBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+// ------------------------------------------------------------ HIP graphs
+//
+// The device work of a call between two host synchronisations (a phase) is
+// captured on a private stream and replayed as one graph launch on the call's
+// stream. Executable graphs are kept per phase and updated in place with the
+// next call's launch parameters; a graph whose node structure changed is
+// instantiated again. Everything a phase touches is allocated before its
+// capture starts and released only after the call has synchronised, and no
+// captured phase contains a memset node (buffers are cleared by kernels).
+
+enum PhaseId { kPhaseTraverse = 0, kPhaseScan, kPhaseSort, kPhaseSupernodes, kPhaseColumns, kPhaseCount };
+
+struct GraphPool {
+    std::mutex mu;
+    std::vector<hipStream_t> streams;  // idle capture streams
+    // idle executable graphs: (phase, node count) -> exec
+    std::vector<std::pair<std::pair<int, size_t>, hipGraphExec_t>> execs;
+    std::vector<hipEvent_t> events;  // idle timing events
+};
+
+// Never destroyed: graphs, streams and events must not be released while the
+// runtime shuts down at process exit.
+GraphPool& graph_pool() {
+    static GraphPool* p = new GraphPool();
+    return *p;
+}
+
+std::atomic<uint64_t> g_graph_instantiations{0}, g_graph_updates{0}, g_graph_launches{0};
+
+class Phase {
+  public:
+    Phase(int id, bool use_graph, hipStream_t run) : id_(id), graph_(use_graph), run_(run) {
+        if (!graph_) return;
+        {
+            std::lock_guard<std::mutex> g(graph_pool().mu);
+            auto& v = graph_pool().streams;
+            if (!v.empty()) {
+                cap_ = v.back();
+                v.pop_back();
+            }
+        }
+        if (!cap_) chk(hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking));
+        chk(hipStreamBeginCapture(cap_, hipStreamCaptureModeRelaxed));
+        capturing_ = true;
+    }
+    Phase(const Phase&) = delete;
+    Phase& operator=(const Phase&) = delete;
+
+    // stream the phase's work is enqueued on
+    hipStream_t stream() const { return graph_ ? cap_ : run_; }
+
+    // end the capture and launch the phase's graph on the call's stream
+    void launch() {
+        if (!graph_) return;
+        hipGraph_t g = nullptr;
+        capturing_ = false;
+        chk(hipStreamEndCapture(cap_, &g));
+        struct GraphGuard {
+            hipGraph_t g;
+            ~GraphGuard() {
+                if (g) (void)hipGraphDestroy(g);
+            }
+        } gg{g};
+        size_t nodes = 0;
+        chk(hipGraphGetNodes(g, nullptr, &nodes));
+        if (nodes == 0) return;
+        key_ = {id_, nodes};
+        {
+            std::lock_guard<std::mutex> lk(graph_pool().mu);
+            auto& v = graph_pool().execs;
+            for (size_t i = 0; i < v.size(); ++i)
+                if (v[i].first == key_) {
+                    exec_ = v[i].second;
+                    v.erase(v.begin() + (long)i);
+                    break;
+                }
+        }
+        if (exec_) {
+            hipGraphNode_t bad = nullptr;
+            hipGraphExecUpdateResult res = hipGraphExecUpdateSuccess;
+            if (hipGraphExecUpdate(exec_, g, &bad, &res) != hipSuccess || res != hipGraphExecUpdateSuccess) {
+                (void)hipGetLastError();
+                (void)hipGraphExecDestroy(exec_);
+                exec_ = nullptr;
+            } else {
+                g_graph_updates.fetch_add(1);
+            }
+        }
+        if (!exec_) {
+            chk(hipGraphInstantiate(&exec_, g, nullptr, nullptr, 0));
+            g_graph_instantiations.fetch_add(1);
+        }
+        chk(hipGraphLaunch(exec_, run_));
+        g_graph_launches.fetch_add(1);
+        launched_ = true;
+    }
+
+    // the caller has synchronised with the call's stream: the graph is idle
+    void done() { finished_ = true; }
+
+    ~Phase() {
+        if (capturing_) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(cap_, &g);
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+        }
+        if (exec_) {
+            if (launched_ && !finished_) (void)hipStreamSynchronize(run_);
+            std::lock_guard<std::mutex> lk(graph_pool().mu);
+            auto& v = graph_pool().execs;
+            v.emplace_back(key_, exec_);
+            // bounded: at most 64 idle executable graphs
+            if (v.size() > 64) {
+                (void)hipGraphExecDestroy(v.front().second);
+                v.erase(v.begin());
+            }
+        }
+        if (cap_) {
+            std::lock_guard<std::mutex> lk(graph_pool().mu);
+            graph_pool().streams.push_back(cap_);
+        }
+    }
+
+  private:
+    int id_;
+    bool graph_;
+    hipStream_t run_;
+    hipStream_t cap_ = nullptr;
+    hipGraphExec_t exec_ = nullptr;
+    std::pair<int, size_t> key_{-1, 0};
+    bool capturing_ = false, launched_ = false, finished_ = false;
+};
+
+// Five timing events taken from a process-wide pool for the length of a call.
+struct EventSet {
+    hipEvent_t e[5] = {};
+    EventSet() {
+        std::lock_guard<std::mutex> lk(graph_pool().mu);
+        auto& v = graph_pool().events;
+        for (auto& x : e) {
+            if (!v.empty()) {
+                x = v.back();
+                v.pop_back();
+            }
+        }
+    }
+    EventSet(const EventSet&) = delete;
+    EventSet& operator=(const EventSet&) = delete;
+    hipEvent_t operator[](int i) {
+        if (!e[i]) chk(hipEventCreate(&e[i]));
+        return e[i];
+    }
+    ~EventSet() {
+        std::lock_guard<std::mutex> lk(graph_pool().mu);
+        for (auto x : e)
+            if (x) graph_pool().events.push_back(x);
+    }
+};
+
 // Slot state is kept initialised between calls: every source leaves its
 // pending bitmap clear and its labels in a used-up range, so a later call with
 // the same layout can start at once.
@@ -285,6 +459,7 @@ int check_csr_host(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<
 struct ResultOwner {
     // host arrays (malloc) or device buffers shared by the results of one call
     std::vector<void*> host;
+    std::shared_ptr<void> shared_host;
     std::shared_ptr<std::vector<DBuf>> dev;
 };
 
@@ -317,6 +492,8 @@ struct Plan {
     int32_t max_super;  // <= 0: unbounded
     uint32_t flags;
     int64_t budget;
+    bool window_auto;   // window span, mapping and sources in flight are the tuner's
+    bool allow_trials;  // the tuner may time trial launches in this call
 };
 
 // Traversal mapping. One wavefront per source is the default: per-source
@@ -342,6 +519,46 @@ int32_t auto_window(int64_t N) {
     return 16;
 }
 
+// ------------------------------------------------------------ autotuner
+//
+// Window span, traversal mapping and the number of sources in flight change
+// only the speed, never the result. For a size class that has not been seen
+// yet (device, log2 of the largest n, mean row length, batch size) and a call
+// with enough sources, the tuner times every candidate on the same stratified
+// sample of the call's sources (8 per slot), keeps the fastest, and reuses it
+// for later calls of the class. Smaller calls use the defaults.
+
+struct TuneKey {
+    int cus, n_log2, deg_bucket, batch_log2;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(cus, n_log2, deg_bucket, batch_log2) < std::tie(o.cus, o.n_log2, o.deg_bucket, o.batch_log2);
+    }
+};
+
+struct TuneChoice {
+    int mapping;     // 3 byte states, 0 32-bit labels, 2 eight wavefronts per source
+    int32_t window;  // threshold-window span
+    int slots_div;   // sources in flight = resident wavefronts / slots_div
+};
+
+constexpr TuneChoice kTuneCandidates[] = {
+    {3, 16, 1}, {3, 8, 1}, {3, 32, 1}, {3, 64, 1}, {3, 16, 2}, {3, 16, 4}, {0, 16, 1}, {2, 16, 1},
+};
+constexpr int64_t kTuneMinSources = 65536;  // calls with fewer sources use the defaults
+constexpr int kTuneSamplesPerSlot = 8;
+
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneChoice>& tune_table() {
+    static auto* t = new std::map<TuneKey, TuneChoice>();
+    return *t;
+}
+
+int ceil_log2(int64_t v) {
+    int b = 0;
+    while (b < 62 && (int64_t(1) << b) < v) ++b;
+    return b;
+}
+
 struct EngineOut {
     int status = GSOFA_OK;
     std::vector<int> job_status;
@@ -364,6 +581,22 @@ int64_t pool_estimate(int64_t nrows, int64_t nnz) {
 // take up to a third of the rest in 4-byte entries.
 int64_t budget_for(int64_t nrows, int64_t nnz, int64_t nslots, const SlotLayout& lay) {
     return fixed_bytes(nrows, nnz) + 2 * nslots * lay.bytes_per_slot + 12 * pool_estimate(nrows, nnz);
+}
+
+// out[j] = row_ptr_j[n_j]: the entry count of every matrix of a batch.
+__global__ void k_gather_last(int32_t njobs, const Job* jobs, int64_t* out) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= njobs) return;
+    out[j] = jobs[j].n > 0 ? (int64_t)jobs[j].row_ptr[jobs[j].n] : 0;
+}
+
+// out[j] = a[job_row_base[j]] for j < njobs, out[njobs] = a[nrows]: the values
+// of a global pointer array at the matrix boundaries.
+__global__ void k_gather_bounds(int32_t njobs, const int64_t* job_row_base, int64_t nrows, const int64_t* a,
+                                int64_t* out) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > njobs) return;
+    out[j] = a[j < njobs ? job_row_base[j] : nrows];
 }
 
 __global__ void k_rebase_ptr(int32_t njobs, const int64_t* job_row_base, const int32_t* job_n,
@@ -407,14 +640,25 @@ struct Engine {
         std::vector<Job> jobs(nj);
         DBuf in_rp, in_ci;
         if (on_device) {
+            // every matrix's entry count (row_ptr[n]) in one gather and one copy
             for (int32_t j = 0; j < nj; ++j) {
-                int32_t last = 0;
-                if (mats[j].n > 0) chk(hipMemcpyAsync(&last, mats[j].rp + mats[j].n, 4, hipMemcpyDeviceToHost, st));
-                chk(hipStreamSynchronize(st));
-                if (last < 0) jstat[j] = GSOFA_EINVAL;
-                nnz[j] = last;
                 jobs[j].row_ptr = mats[j].rp;
                 jobs[j].col_idx = mats[j].ci;
+                jobs[j].n = mats[j].n;
+            }
+            DBuf d_tab(sizeof(Job) * std::max(nj, 1)), d_last(8 * std::max(nj, 1));
+            PinnedBuf h_last(8 * std::max(nj, 1));
+            chk(hipMemcpyAsync(d_tab.p, jobs.data(), sizeof(Job) * nj, hipMemcpyHostToDevice, st));
+            if (nj > 0)
+                hipLaunchKernelGGL(k_gather_last, dim3((nj + 255) / 256), dim3(256), 0, st, nj, d_tab.as<Job>(),
+                                   d_last.as<int64_t>());
+            chk(hipGetLastError());
+            chk(hipMemcpyAsync(h_last.p, d_last.p, 8 * nj, hipMemcpyDeviceToHost, st));
+            chk(hipStreamSynchronize(st));
+            for (int32_t j = 0; j < nj; ++j) {
+                const int64_t last = h_last.as<int64_t>()[j];
+                if (last < 0) jstat[j] = GSOFA_EINVAL;
+                nnz[j] = std::max<int64_t>(last, 0);
             }
         } else {
             std::vector<int64_t> rp_off(nj), ci_off(nj);
@@ -493,20 +737,54 @@ struct Engine {
         int64_t budget = plan.budget > 0 ? plan.budget : (int64_t)(di.free_b * 0.9);
         const int64_t fixed = fixed_bytes(nrows, total_nnz);
         if (budget < fixed + lay.bytes_per_slot) throw Status{GSOFA_ENOMEM};
-        const int mapping = choose_mapping(plan.flags, plan.window);
-        int64_t want = plan.nslots > 0 ? plan.nslots : (int64_t)traverse_resident_slots(di.cus, mapping);
-        want = std::min<int64_t>(want, std::max<int64_t>(items, 1));
-        const int64_t slot_room = (budget - fixed) / 2;  // half of the rest for slots
-        int64_t nslots = std::min<int64_t>(want, std::max<int64_t>(slot_room / lay.bytes_per_slot, 1));
-        nslots = std::max<int64_t>(nslots, 1);
-        // the one-wavefront mapping launches whole blocks of 4 wavefronts
-        if ((mapping == 0 || mapping == 3) && nslots > 4) nslots = nslots / 4 * 4;
+        const int64_t slot_fit = std::max<int64_t>((budget - fixed) / 2 / lay.bytes_per_slot, 1);
+        // sources in flight for a mapping: the resident wavefronts (or blocks),
+        // divided by div, within half of the memory left after the fixed part
+        auto plan_slots = [&](int map, int div) {
+            int64_t want = plan.nslots > 0 ? plan.nslots : (int64_t)traverse_resident_slots(di.cus, map) / div;
+            want = std::min<int64_t>(want, std::max<int64_t>(items, 1));
+            int64_t ns = std::max<int64_t>(std::min<int64_t>(want, slot_fit), 1);
+            // the one-wavefront mappings launch whole blocks of 4 wavefronts
+            if ((map == 0 || map == 3) && ns > 4) ns = ns / 4 * 4;
+            return ns;
+        };
+        int mapping = choose_mapping(plan.flags, plan.window);
+        int slots_div = 1;
+        double t_tune = 0;
+        if (plan.window_auto) {
+            const TuneKey key{di.cus, ceil_log2(N), ceil_log2(std::max<int64_t>(total_nnz * 4 / std::max<int64_t>(nrows, 1), 1)),
+                              nj > 1 ? ceil_log2(nj) : 0};
+            bool found = false;
+            {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                auto it = tune_table().find(key);
+                if (it != tune_table().end()) {
+                    mapping = it->second.mapping;
+                    plan.window = it->second.window;
+                    slots_div = it->second.slots_div;
+                    found = true;
+                }
+            }
+            const bool force = (plan.flags & GSOFA_TUNE_NOW) != 0;
+            if ((!found || force) && plan.allow_trials && (items >= kTuneMinSources || force)) {
+                const double tt0 = now_ms();
+                const TuneChoice c = tune(jt, nj, N, items, lay, budget, fixed, total_nnz, nrows, d_jobs, plan_slots);
+                t_tune = now_ms() - tt0;
+                mapping = c.mapping;
+                plan.window = c.window;
+                slots_div = c.slots_div;
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                tune_table()[key] = c;
+            }
+        }
+        const int64_t nslots = plan_slots(mapping, slots_div);
 
         int64_t pool_cap = pool_estimate(nrows, total_nnz);
         const int64_t pool_room = (budget - fixed - nslots * lay.bytes_per_slot) / 4 / 3;
         pool_cap = std::max<int64_t>(std::min<int64_t>(pool_cap, pool_room), nrows + 1024);
 
         auto slots = take_slots(lay, (int32_t)nslots, mapping == 3 ? 1 : 0, st);
+        const bool graphs = (plan.flags & GSOFA_EAGER) == 0;
 
         DBuf row_off(8 * (size_t)std::max<int64_t>(nrows, 1));
         DBuf row_cnt(4 * (size_t)std::max<int64_t>(nrows, 1));
@@ -515,22 +793,15 @@ struct Engine {
         DBuf jst(sizeof(JobStats) * std::max(nj, 1));
         DBuf pool(4 * (size_t)pool_cap);
         DBuf d_row_job;
-        if (nj > 1) {
-            d_row_job = DBuf(4 * (size_t)std::max<int64_t>(nrows, 1));
-            chk(launch_row_job(d_jobs.as<Job>(), nj, N, d_row_job.as<int32_t>(), st));
-        }
-        chk(launch_zero_i32(counters.as<int32_t>(), 16, st));
-        chk(launch_zero_i32(jst.as<int32_t>(), (int64_t)(sizeof(JobStats) / 4) * nj, st));
+        if (nj > 1) d_row_job = DBuf(4 * (size_t)std::max<int64_t>(nrows, 1));
+        // job statistics and the pool tail come back through pinned memory
+        PinnedBuf h_stats(sizeof(JobStats) * (size_t)std::max(nj, 1) + 64);
+        JobStats* hst = h_stats.as<JobStats>();
+        unsigned long long* h_tail =
+            reinterpret_cast<unsigned long long*>(h_stats.as<char>() + sizeof(JobStats) * (size_t)std::max(nj, 1));
 
-        // ev[0]/ev[4]: traversal kernel; ev[1]..ev[3]: assembly and supernode phases
-        hipEvent_t ev[5];
-        for (auto& e : ev) chk(hipEventCreate(&e));
-        struct EvGuard {
-            hipEvent_t* e;
-            ~EvGuard() {
-                for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e[i]);
-            }
-        } evg{ev};
+        // ev[0]/ev[4]: traversal phase; ev[1]..ev[3]: emit, supernode and column phases
+        EventSet ev;
 
         TraverseArgs ta{};
         ta.jobs = d_jobs.as<Job>();
@@ -553,14 +824,21 @@ struct Engine {
         ta.flags = plan.flags;
         ta.mapping = mapping;
         chk(hipEventRecord(ev[0], st));
-        chk(launch_traverse(ta, st));
-        chk(hipEventRecord(ev[4], st));
-
-        std::vector<JobStats> hst(nj);
-        unsigned long long tail = 0;
-        chk(hipMemcpyAsync(hst.data(), jst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, st));
-        chk(hipMemcpyAsync(&tail, counters.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, st));
-        chk(hipStreamSynchronize(st));
+        {
+            // phase 1: one persistent traversal launch over every source of every matrix
+            Phase ph(kPhaseTraverse, graphs, st);
+            const hipStream_t s = ph.stream();
+            if (nj > 1) chk(launch_row_job(d_jobs.as<Job>(), nj, N, d_row_job.as<int32_t>(), s));
+            chk(launch_zero_i32(counters.as<int32_t>(), 16, s));
+            chk(launch_zero_i32(jst.as<int32_t>(), (int64_t)(sizeof(JobStats) / 4) * nj, s));
+            chk(launch_traverse(ta, s));
+            chk(hipMemcpyAsync(hst, jst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, s));
+            chk(hipMemcpyAsync(h_tail, counters.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, s));
+            ph.launch();
+            chk(hipEventRecord(ev[4], st));
+            chk(hipStreamSynchronize(st));
+            ph.done();
+        }
 
         bool overflow = false;
         float t_trav_extra = 0;
@@ -595,7 +873,7 @@ struct Engine {
             ta.pool = pool.as<int32_t>();
             ta.pool_cap = new_cap;
             // stats were already counted for these rows in the first pass: keep a copy
-            std::vector<JobStats> keep = hst;
+            std::vector<JobStats> keep(hst, hst + nj);
             chk(launch_zero_i32(jst.as<int32_t>(), (int64_t)(sizeof(JobStats) / 4) * nj, st));
             float first_ms = 0;
             chk(hipEventElapsedTime(&first_ms, ev[0], ev[4]));
@@ -603,8 +881,8 @@ struct Engine {
             chk(hipEventRecord(ev[0], st));
             chk(launch_traverse(ta, st));
             chk(hipEventRecord(ev[4], st));
-            chk(hipMemcpyAsync(hst.data(), jst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, st));
-            chk(hipMemcpyAsync(&tail, counters.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, st));
+            chk(hipMemcpyAsync(hst, jst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, st));
+            chk(hipMemcpyAsync(h_tail, counters.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, st));
             chk(hipStreamSynchronize(st));
             for (int32_t q = 0; q < nj; ++q) {
                 if (hst[q].err & kErrOverflow) throw Status{GSOFA_ENOMEM};
@@ -621,58 +899,40 @@ struct Engine {
         chk(hipEventRecord(ev[1], st));
         give_slots(std::move(slots));
         if (total_nnz > 0)
-            g_fill_ratio.store(std::max(4.0, (double)tail / (double)total_nnz));
+            g_fill_ratio.store(std::max(4.0, (double)*h_tail / (double)total_nnz));
 
-        // ---- assembly: counts -> pointers -> sorted rows (U CSR, L CSR)
+        // ---- phase 2: counts -> row pointers of U and L, and the totals
         DBuf scan_scr(8 * (size_t)scan_scratch_elems(nrows + 1) + 64);
         DBuf u_ptr(8 * (size_t)(nrows + 1)), l_rptr(8 * (size_t)(nrows + 1));
-        chk(launch_scan_counts(row_cnt.as<int32_t>(), row_lcnt.as<int32_t>(), nrows, u_ptr.as<int64_t>(),
-                               scan_scr.as<int64_t>(), st));
-        chk(launch_scan_counts(row_lcnt.as<int32_t>(), nullptr, nrows, l_rptr.as<int64_t>(),
-                               scan_scr.as<int64_t>(), st));
-        int64_t tot[2] = {0, 0};
-        chk(hipMemcpyAsync(&tot[0], u_ptr.as<int64_t>() + nrows, 8, hipMemcpyDeviceToHost, st));
-        chk(hipMemcpyAsync(&tot[1], l_rptr.as<int64_t>() + nrows, 8, hipMemcpyDeviceToHost, st));
-        chk(hipStreamSynchronize(st));
-        const int64_t nnz_u = tot[0], nnz_l = tot[1];
+        PinnedBuf h_tot(16);
+        {
+            Phase ph(kPhaseScan, graphs, st);
+            const hipStream_t s = ph.stream();
+            chk(launch_scan_counts(row_cnt.as<int32_t>(), row_lcnt.as<int32_t>(), nrows, u_ptr.as<int64_t>(),
+                                   scan_scr.as<int64_t>(), s));
+            chk(launch_scan_counts(row_lcnt.as<int32_t>(), nullptr, nrows, l_rptr.as<int64_t>(),
+                                   scan_scr.as<int64_t>(), s));
+            chk(hipMemcpyAsync(h_tot.as<int64_t>(), u_ptr.as<int64_t>() + nrows, 8, hipMemcpyDeviceToHost, s));
+            chk(hipMemcpyAsync(h_tot.as<int64_t>() + 1, l_rptr.as<int64_t>() + nrows, 8, hipMemcpyDeviceToHost, s));
+            ph.launch();
+            chk(hipStreamSynchronize(st));
+            ph.done();
+        }
+        const int64_t nnz_u = h_tot.as<int64_t>()[0], nnz_l = h_tot.as<int64_t>()[1];
+
+        // ---- everything the remaining phases touch is allocated up front, so
+        // that they can be captured and replayed without host work in between
+        const bool want_sn = (plan.flags & GSOFA_NO_SUPERNODES) == 0;
+        const bool have_sn = want_sn && nrows > 0;
+        const bool l_csr = (plan.flags & GSOFA_L_CSR) != 0;
         DBuf u_idx(4 * (size_t)std::max<int64_t>(nnz_u, 1)), l_ridx(4 * (size_t)std::max<int64_t>(nnz_l, 1));
         DBuf big_list(4 * (size_t)std::max<int64_t>(nrows, 1)), big_cnt(64);
-        DBuf d_jrb(8 * std::max(nj, 1)), d_jn(4 * std::max(nj, 1));
-        std::vector<int32_t> jn(nj);
-        for (int32_t j = 0; j < nj; ++j) jn[j] = mats[j].n;
-        chk(hipMemcpyAsync(d_jrb.p, row_base.data(), 8 * nj, hipMemcpyHostToDevice, st));
-        chk(hipMemcpyAsync(d_jn.p, jn.data(), 4 * nj, hipMemcpyHostToDevice, st));
-        // rows of the global row space -> job in the user's order
-        DBuf row_job_user;
-        RowSpace rs{nrows, nullptr, nullptr};
-        if (nj > 1) {
-            row_job_user = DBuf(4 * (size_t)std::max<int64_t>(nrows, 1));
-            // a job table in user order for k_row_job
-            std::vector<Job> ju(nj);
-            for (int32_t j = 0; j < nj; ++j) {
-                ju[j] = jobs[j];
-                ju[j].n = mats[j].n;
-                ju[j].row_base = row_base[j];
-            }
-            DBuf d_ju(sizeof(Job) * nj);
-            chk(hipMemcpyAsync(d_ju.p, ju.data(), sizeof(Job) * nj, hipMemcpyHostToDevice, st));
-            chk(launch_row_job(d_ju.as<Job>(), nj, N, row_job_user.as<int32_t>(), st));
-            chk(hipStreamSynchronize(st));
-            rs.row_job = row_job_user.as<int32_t>();
-            rs.job_row_base = d_jrb.as<int64_t>();
-        }
-        chk(launch_sort_rows(rs, row_off.as<int64_t>(), row_cnt.as<int32_t>(), row_lcnt.as<int32_t>(),
-                             pool.as<int32_t>(), u_ptr.as<int64_t>(), u_idx.as<int32_t>(), l_rptr.as<int64_t>(),
-                             l_ridx.as<int32_t>(), big_list.as<int32_t>(), big_cnt.as<int32_t>(), st));
-        pool.reset();
 
-        // ---- supernodes (Definition T3 per block of max_supernode rows)
-        const bool want_sn = (plan.flags & GSOFA_NO_SUPERNODES) == 0;
-        DBuf is_start, start_scan, xsup_all, supno_all;
-        chk(hipEventRecord(ev[2], st));
-        if (want_sn && nrows > 0) {
-            std::vector<int64_t> bf;
-            std::vector<int32_t> bl;
+        // small host tables in one pinned block and one upload: row bases and
+        // sizes per matrix, a job table in the user's order, supernode blocks
+        std::vector<int64_t> bf;
+        std::vector<int32_t> bl;
+        if (have_sn)
             for (int32_t j = 0; j < nj; ++j) {
                 const int64_t M = plan.max_super > 0 ? plan.max_super : std::max<int64_t>(mats[j].n, 1);
                 for (int64_t b = 0; b < mats[j].n; b += M) {
@@ -680,95 +940,190 @@ struct Engine {
                     bl.push_back((int32_t)std::min<int64_t>(M, mats[j].n - b));
                 }
             }
-            DBuf d_bf(8 * bf.size()), d_bl(4 * bl.size());
-            chk(hipMemcpyAsync(d_bf.p, bf.data(), 8 * bf.size(), hipMemcpyHostToDevice, st));
-            chk(hipMemcpyAsync(d_bl.p, bl.data(), 4 * bl.size(), hipMemcpyHostToDevice, st));
+        const int64_t nbk = (int64_t)bf.size();
+        auto up8 = [](int64_t b) { return (b + 15) & ~int64_t(15); };
+        const int64_t o_jrb = 0, o_jn = o_jrb + up8(8 * (int64_t)nj), o_ju = o_jn + up8(4 * (int64_t)nj),
+                      o_bf = o_ju + up8((int64_t)sizeof(Job) * nj), o_bl = o_bf + up8(8 * nbk),
+                      up_bytes = o_bl + up8(4 * nbk) + 16;
+        PinnedBuf h_up((size_t)up_bytes);
+        DBuf d_up((size_t)up_bytes);
+        {
+            char* c = h_up.as<char>();
+            int64_t* jrb = reinterpret_cast<int64_t*>(c + o_jrb);
+            int32_t* jn = reinterpret_cast<int32_t*>(c + o_jn);
+            Job* ju = reinterpret_cast<Job*>(c + o_ju);
+            for (int32_t j = 0; j < nj; ++j) {
+                jrb[j] = row_base[j];
+                jn[j] = mats[j].n;
+                ju[j] = jobs[j];
+                ju[j].n = mats[j].n;
+                ju[j].row_base = row_base[j];
+            }
+            if (nbk) {
+                std::memcpy(c + o_bf, bf.data(), 8 * (size_t)nbk);
+                std::memcpy(c + o_bl, bl.data(), 4 * (size_t)nbk);
+            }
+        }
+        const int64_t* d_jrb = reinterpret_cast<const int64_t*>(d_up.as<char>() + o_jrb);
+        const int32_t* d_jn = reinterpret_cast<const int32_t*>(d_up.as<char>() + o_jn);
+        const Job* d_ju = reinterpret_cast<const Job*>(d_up.as<char>() + o_ju);
+        const int64_t* d_bf = reinterpret_cast<const int64_t*>(d_up.as<char>() + o_bf);
+        const int32_t* d_bl = reinterpret_cast<const int32_t*>(d_up.as<char>() + o_bl);
+
+        // rows of the global row space -> matrix in the user's order
+        DBuf row_job_user;
+        RowSpace rs{nrows, nullptr, nullptr};
+        if (nj > 1) {
+            row_job_user = DBuf(4 * (size_t)std::max<int64_t>(nrows, 1));
+            rs.row_job = row_job_user.as<int32_t>();
+            rs.job_row_base = d_jrb;
+        }
+        DBuf is_start, start_scan, xsup_all, supno_all;
+        if (have_sn) {
             is_start = DBuf(4 * (size_t)nrows);
             start_scan = DBuf(8 * (size_t)(nrows + 1));
             xsup_all = DBuf(4 * (size_t)(nrows + nj));
             supno_all = DBuf(4 * (size_t)nrows);
-            chk(launch_supernodes(rs, (int64_t)bf.size(), d_bf.as<int64_t>(), d_bl.as<int32_t>(),
-                                  u_ptr.as<int64_t>(), l_rptr.as<int64_t>(), l_ridx.as<int32_t>(),
-                                  is_start.as<int32_t>(), st));
-            chk(launch_scan_counts(is_start.as<int32_t>(), nullptr, nrows, start_scan.as<int64_t>(),
-                                   scan_scr.as<int64_t>(), st));
-            chk(launch_supernode_assemble(rs, nj, is_start.as<int32_t>(), start_scan.as<int64_t>(),
-                                          xsup_all.as<int32_t>(), supno_all.as<int32_t>(), st));
-            chk(launch_supernode_terminals(nj, d_jrb.as<int64_t>(), d_jn.as<int32_t>(), start_scan.as<int64_t>(),
-                                           xsup_all.as<int32_t>(), st));
-            chk(hipStreamSynchronize(st));
         }
-        chk(hipEventRecord(ev[3], st));
-
-        // ---- L column-wise
-        const bool l_csr = (plan.flags & GSOFA_L_CSR) != 0;
-        DBuf l_cptr, l_cidx;
+        DBuf l_cptr, l_cidx, col_cnt, cursor, ctmp;
         if (!l_csr) {
             l_cptr = DBuf(8 * (size_t)(nrows + 1));
             l_cidx = DBuf(4 * (size_t)std::max<int64_t>(nnz_l, 1));
-            DBuf col_cnt(4 * (size_t)std::max<int64_t>(nrows, 1)), cursor(4 * (size_t)std::max<int64_t>(nrows, 1));
-            DBuf tmp(4 * (size_t)std::max<int64_t>(nnz_l, 1));
-            chk(launch_transpose_l(rs, l_rptr.as<int64_t>(), l_ridx.as<int32_t>(), col_cnt.as<int32_t>(),
-                                   l_cptr.as<int64_t>(), l_cidx.as<int32_t>(), scan_scr.as<int64_t>(),
-                                   cursor.as<int32_t>(), tmp.as<int32_t>(), big_list.as<int32_t>(),
-                                   big_cnt.as<int32_t>(), st));
-            chk(hipStreamSynchronize(st));
+            col_cnt = DBuf(4 * (size_t)std::max<int64_t>(nrows, 1));
+            cursor = DBuf(4 * (size_t)std::max<int64_t>(nrows, 1));
+            ctmp = DBuf(4 * (size_t)std::max<int64_t>(nnz_l, 1));
         }
-        float t_trav = 0, t_emit = 0, t_sn = 0, t_l = 0;
-        chk(hipEventSynchronize(ev[3]));
+        const int64_t* Lp = l_csr ? l_rptr.as<int64_t>() : l_cptr.as<int64_t>();
+        const int32_t* Li = l_csr ? l_ridx.as<int32_t>() : l_cidx.as<int32_t>();
+        // per-matrix pointer arrays (each starting at 0) side by side: matrix j
+        // owns entries [row_base_j + j, row_base_j + j + n_j]
+        DBuf u_ptr_loc, l_ptr_loc;
+        const int64_t* Up_loc = u_ptr.as<int64_t>();
+        const int64_t* Lp_loc = Lp;
+        if (nj > 1) {
+            u_ptr_loc = DBuf(8 * (size_t)(nrows + nj));
+            l_ptr_loc = DBuf(8 * (size_t)(nrows + nj));
+            Up_loc = u_ptr_loc.as<int64_t>();
+            Lp_loc = l_ptr_loc.as<int64_t>();
+        }
+        // pointer values at the matrix boundaries, for the result headers
+        DBuf d_b(8 * 3 * (size_t)(nj + 1));
+        PinnedBuf h_b(8 * 3 * (size_t)(nj + 1));
+
+        // ---- phase 3: sorted rows of U (CSR) and L (CSR)
+        Phase ph_sort(kPhaseSort, graphs, st);
+        {
+            const hipStream_t s = ph_sort.stream();
+            chk(hipMemcpyAsync(d_up.p, h_up.p, (size_t)up_bytes, hipMemcpyHostToDevice, s));
+            if (nj > 1) chk(launch_row_job(d_ju, nj, N, row_job_user.as<int32_t>(), s));
+            chk(launch_sort_rows(rs, row_off.as<int64_t>(), row_cnt.as<int32_t>(), row_lcnt.as<int32_t>(),
+                                 pool.as<int32_t>(), u_ptr.as<int64_t>(), u_idx.as<int32_t>(),
+                                 l_rptr.as<int64_t>(), l_ridx.as<int32_t>(), big_list.as<int32_t>(),
+                                 big_cnt.as<int32_t>(), s));
+            ph_sort.launch();
+        }
+        chk(hipEventRecord(ev[2], st));
+
+        // ---- phase 4: supernodes (Definition T3 per block of max_supernode rows)
+        Phase ph_sn(kPhaseSupernodes, graphs, st);
+        if (have_sn) {
+            const hipStream_t s = ph_sn.stream();
+            chk(launch_supernodes(rs, nbk, d_bf, d_bl, u_ptr.as<int64_t>(), l_rptr.as<int64_t>(),
+                                  l_ridx.as<int32_t>(), is_start.as<int32_t>(), s));
+            chk(launch_scan_counts(is_start.as<int32_t>(), nullptr, nrows, start_scan.as<int64_t>(),
+                                   scan_scr.as<int64_t>(), s));
+            chk(launch_supernode_assemble(rs, nj, is_start.as<int32_t>(), start_scan.as<int64_t>(),
+                                          xsup_all.as<int32_t>(), supno_all.as<int32_t>(), s));
+            chk(launch_supernode_terminals(nj, d_jrb, d_jn, start_scan.as<int64_t>(), xsup_all.as<int32_t>(), s));
+        }
+        ph_sn.launch();
+        chk(hipEventRecord(ev[3], st));
+
+        // ---- phase 5: L column-wise, per-matrix pointers, boundary values
+        Phase ph_col(kPhaseColumns, graphs, st);
+        {
+            const hipStream_t s = ph_col.stream();
+            if (!l_csr)
+                chk(launch_transpose_l(rs, l_rptr.as<int64_t>(), l_ridx.as<int32_t>(), col_cnt.as<int32_t>(),
+                                       l_cptr.as<int64_t>(), l_cidx.as<int32_t>(), scan_scr.as<int64_t>(),
+                                       cursor.as<int32_t>(), ctmp.as<int32_t>(), big_list.as<int32_t>(),
+                                       big_cnt.as<int32_t>(), s));
+            if (nj > 1) {
+                const unsigned gx = (unsigned)std::min<int64_t>((N + 256) / 256, 64);
+                hipLaunchKernelGGL(k_rebase_ptr, dim3(gx, nj), dim3(256), 0, s, nj, d_jrb, d_jn,
+                                   u_ptr.as<int64_t>(), u_ptr_loc.as<int64_t>());
+                hipLaunchKernelGGL(k_rebase_ptr, dim3(gx, nj), dim3(256), 0, s, nj, d_jrb, d_jn, Lp,
+                                   l_ptr_loc.as<int64_t>());
+            }
+            const dim3 gb((nj + 1 + 255) / 256);
+            hipLaunchKernelGGL(k_gather_bounds, gb, dim3(256), 0, s, nj, d_jrb, nrows, u_ptr.as<int64_t>(),
+                               d_b.as<int64_t>());
+            hipLaunchKernelGGL(k_gather_bounds, gb, dim3(256), 0, s, nj, d_jrb, nrows, Lp,
+                               d_b.as<int64_t>() + (nj + 1));
+            if (have_sn)
+                hipLaunchKernelGGL(k_gather_bounds, gb, dim3(256), 0, s, nj, d_jrb, nrows, start_scan.as<int64_t>(),
+                                   d_b.as<int64_t>() + 2 * (nj + 1));
+            chk(hipGetLastError());
+            chk(hipMemcpyAsync(h_b.p, d_b.p, 8 * 3 * (size_t)(nj + 1), hipMemcpyDeviceToHost, s));
+            ph_col.launch();
+        }
+        chk(hipStreamSynchronize(st));
+        ph_sort.done();
+        ph_sn.done();
+        ph_col.done();
+        pool.reset();
+
+        float t_trav = 0, t_emit = 0, t_sn = 0;
         chk(hipEventElapsedTime(&t_trav, ev[0], ev[4]));
         t_trav += t_trav_extra;
         chk(hipEventElapsedTime(&t_emit, ev[1], ev[2]));
         chk(hipEventElapsedTime(&t_sn, ev[2], ev[3]));
-        (void)t_l;
 
         // ---- results
-        std::vector<int64_t> h_sn_scan;  // start scan at job boundaries
-        std::vector<int64_t> h_u_ptr, h_l_ptr;
-        const int64_t* Lp = l_csr ? l_rptr.as<int64_t>() : l_cptr.as<int64_t>();
-        const int32_t* Li = l_csr ? l_ridx.as<int32_t>() : l_cidx.as<int32_t>();
         const bool dev_out = (plan.flags & GSOFA_RESULT_ON_DEVICE) != 0;
-
-        std::vector<int64_t> ujb(nj + 1), ljb(nj + 1), sjb(nj + 1);
+        std::vector<int64_t> ujb(nj + 1), ljb(nj + 1), sjb(nj + 1, 0);
         {
-            // pointer values at job boundaries
-            std::vector<int64_t> hu(nrows + 1), hl(nrows + 1), hs;
-            chk(hipMemcpyAsync(hu.data(), u_ptr.p, 8 * (nrows + 1), hipMemcpyDeviceToHost, st));
-            chk(hipMemcpyAsync(hl.data(), Lp, 8 * (nrows + 1), hipMemcpyDeviceToHost, st));
-            if (want_sn && nrows > 0) {
-                hs.resize(nrows + 1);
-                chk(hipMemcpyAsync(hs.data(), start_scan.p, 8 * (nrows + 1), hipMemcpyDeviceToHost, st));
-            }
-            chk(hipStreamSynchronize(st));
+            const int64_t* hb = h_b.as<int64_t>();
             for (int32_t j = 0; j <= nj; ++j) {
-                const int64_t b = j < nj ? row_base[j] : nrows;
-                ujb[j] = hu[b];
-                ljb[j] = hl[b];
-                sjb[j] = hs.empty() ? 0 : hs[b];
-            }
-            if (!dev_out) {
-                h_u_ptr.swap(hu);
-                h_l_ptr.swap(hl);
+                ujb[j] = hb[j];
+                ljb[j] = hb[nj + 1 + j];
+                if (have_sn) sjb[j] = hb[2 * (nj + 1) + j];
             }
         }
+        const int64_t nptr = nrows + std::max(nj, 1);
 
+        // host results: every array copied once into one block shared by the
+        // results of this call (freed with the last of them)
+        std::shared_ptr<void> hblock;
+        int64_t *h_up_ptr = nullptr, *h_lp_ptr = nullptr;
+        int32_t *h_ui = nullptr, *h_li = nullptr, *h_xs = nullptr, *h_sn = nullptr;
         std::shared_ptr<std::vector<DBuf>> keep;
-        DBuf u_ptr_loc, l_ptr_loc;
-        if (dev_out) {
-            if (nj > 1) {
-                u_ptr_loc = DBuf(8 * (size_t)(nrows + nj));
-                l_ptr_loc = DBuf(8 * (size_t)(nrows + nj));
-                const unsigned gx = (unsigned)std::min<int64_t>((N + 256) / 256, 64);
-                hipLaunchKernelGGL(k_rebase_ptr, dim3(gx, nj), dim3(256), 0, st, nj, d_jrb.as<int64_t>(),
-                                   d_jn.as<int32_t>(), u_ptr.as<int64_t>(), u_ptr_loc.as<int64_t>());
-                hipLaunchKernelGGL(k_rebase_ptr, dim3(gx, nj), dim3(256), 0, st, nj, d_jrb.as<int64_t>(),
-                                   d_jn.as<int32_t>(), Lp, l_ptr_loc.as<int64_t>());
-                chk(hipGetLastError());
-                chk(hipStreamSynchronize(st));
+        if (!dev_out) {
+            const size_t bytes = 8 * 2 * (size_t)nptr + 4 * (size_t)(nnz_u + nnz_l) +
+                                 (have_sn ? 4 * (size_t)(nrows + nj + nrows) : 0) + 64;
+            void* blk = std::malloc(bytes);
+            if (!blk) throw Status{GSOFA_ENOMEM};
+            hblock = std::shared_ptr<void>(blk, [](void* q) { std::free(q); });
+            h_up_ptr = static_cast<int64_t*>(blk);
+            h_lp_ptr = h_up_ptr + nptr;
+            h_ui = reinterpret_cast<int32_t*>(h_lp_ptr + nptr);
+            h_li = h_ui + nnz_u;
+            h_xs = h_li + nnz_l;
+            h_sn = h_xs + (have_sn ? nrows + nj : 0);
+            chk(hipMemcpyAsync(h_up_ptr, Up_loc, 8 * (size_t)nptr, hipMemcpyDeviceToHost, st));
+            chk(hipMemcpyAsync(h_lp_ptr, Lp_loc, 8 * (size_t)nptr, hipMemcpyDeviceToHost, st));
+            if (nnz_u) chk(hipMemcpyAsync(h_ui, u_idx.p, 4 * (size_t)nnz_u, hipMemcpyDeviceToHost, st));
+            if (nnz_l) chk(hipMemcpyAsync(h_li, Li, 4 * (size_t)nnz_l, hipMemcpyDeviceToHost, st));
+            if (have_sn) {
+                chk(hipMemcpyAsync(h_xs, xsup_all.p, 4 * (size_t)(nrows + nj), hipMemcpyDeviceToHost, st));
+                chk(hipMemcpyAsync(h_sn, supno_all.p, 4 * (size_t)nrows, hipMemcpyDeviceToHost, st));
             }
+            chk(hipStreamSynchronize(st));
+        } else {
             keep = std::make_shared<std::vector<DBuf>>();
         }
 
+        static int32_t zero_xsup = 0;
         for (int32_t j = 0; j < nj; ++j) {
             gsofa_result* r = new_result();
             results[j] = r;
@@ -786,6 +1141,9 @@ struct Engine {
             r->stats.t_traverse_ms = t_trav;
             r->stats.t_emit_ms = t_emit;
             r->stats.t_supernode_ms = t_sn;
+            r->stats.window = plan.window;
+            r->stats.mapping = mapping;
+            r->stats.t_tune_ms = t_tune;
             if (jstat[j] != GSOFA_OK) continue;
             const int64_t n = mats[j].n, b = row_base[j];
             r->nnz_a = nnz[j];
@@ -793,39 +1151,22 @@ struct Engine {
             r->nnz_l = ljb[j + 1] - ljb[j];
             r->fills = r->nnz_u + r->nnz_l - (nnz[j] + n - (int64_t)hst[q].diag);
             r->nsuper = want_sn ? (int32_t)(sjb[j + 1] - sjb[j]) : 0;
+            auto* own = static_cast<ResultOwner*>(r->internal_);
             if (!dev_out) {
-                r->u_ptr = host_array<int64_t>(r, n + 1);
-                r->l_ptr = host_array<int64_t>(r, n + 1);
-                for (int64_t i = 0; i <= n; ++i) {
-                    r->u_ptr[i] = h_u_ptr[b + i] - ujb[j];
-                    r->l_ptr[i] = h_l_ptr[b + i] - ljb[j];
-                }
-                r->u_idx = host_array<int32_t>(r, r->nnz_u);
-                r->l_idx = host_array<int32_t>(r, r->nnz_l);
-                if (r->nnz_u)
-                    chk(hipMemcpyAsync(r->u_idx, u_idx.as<int32_t>() + ujb[j], 4 * r->nnz_u, hipMemcpyDeviceToHost, st));
-                if (r->nnz_l)
-                    chk(hipMemcpyAsync(r->l_idx, Li + ljb[j], 4 * r->nnz_l, hipMemcpyDeviceToHost, st));
+                own->shared_host = hblock;
+                r->u_ptr = h_up_ptr + b + j;
+                r->l_ptr = h_lp_ptr + b + j;
+                r->u_idx = h_ui + ujb[j];
+                r->l_idx = h_li + ljb[j];
                 if (want_sn) {
-                    r->xsup = host_array<int32_t>(r, r->nsuper + 1);
-                    r->supno = host_array<int32_t>(r, n);
-                    r->xsup[0] = 0;
-                    if (n > 0) {
-                        chk(hipMemcpyAsync(r->xsup, xsup_all.as<int32_t>() + sjb[j] + j, 4 * (r->nsuper + 1),
-                                           hipMemcpyDeviceToHost, st));
-                        chk(hipMemcpyAsync(r->supno, supno_all.as<int32_t>() + b, 4 * n, hipMemcpyDeviceToHost, st));
-                    }
+                    // an empty matrix has the one-entry partition {0}
+                    r->xsup = have_sn ? h_xs + sjb[j] + j : &zero_xsup;
+                    r->supno = have_sn ? h_sn + b : nullptr;
                 }
             } else {
-                auto* own = static_cast<ResultOwner*>(r->internal_);
                 own->dev = keep;
-                if (nj > 1) {
-                    r->u_ptr = u_ptr_loc.as<int64_t>() + b + j;
-                    r->l_ptr = l_ptr_loc.as<int64_t>() + b + j;
-                } else {
-                    r->u_ptr = u_ptr.as<int64_t>();
-                    r->l_ptr = const_cast<int64_t*>(Lp);
-                }
+                r->u_ptr = const_cast<int64_t*>(Up_loc) + b + j;
+                r->l_ptr = const_cast<int64_t*>(Lp_loc) + b + j;
                 r->u_idx = u_idx.as<int32_t>() + ujb[j];
                 r->l_idx = const_cast<int32_t*>(Li) + ljb[j];
                 if (want_sn && n > 0) {
@@ -834,11 +1175,10 @@ struct Engine {
                 }
             }
         }
-        chk(hipStreamSynchronize(st));
         if (dev_out) {
-            for (DBuf* b : {&u_idx, &u_ptr, &l_rptr, &l_ridx, &l_cptr, &l_cidx, &xsup_all, &supno_all,
-                            &u_ptr_loc, &l_ptr_loc})
-                b->synced = true;
+            for (DBuf* db : {&u_idx, &u_ptr, &l_rptr, &l_ridx, &l_cptr, &l_cidx, &xsup_all, &supno_all,
+                             &u_ptr_loc, &l_ptr_loc})
+                db->synced = true;
             keep->push_back(std::move(u_idx));
             keep->push_back(std::move(u_ptr));
             if (l_csr) {
@@ -860,6 +1200,84 @@ struct Engine {
             if (jstat[j] != GSOFA_OK && first_bad == GSOFA_OK) first_bad = jstat[j];
         }
         return first_bad;
+    }
+
+    // Times every tuner candidate on one stratified sample of the call's
+    // sources (largest ids first inside each matrix, as in the real order) and
+    // returns the fastest; a candidate must beat the current best by 3% to
+    // replace it, so near-ties keep the earlier (default) one. The sample's
+    // rows go to scratch arrays; the slot sets are left clean for the real run.
+    template <typename PlanSlots>
+    TuneChoice tune(const std::vector<Job>& jt, int32_t nj, int64_t N, int64_t items, const SlotLayout& lay,
+                    int64_t budget, int64_t fixed, int64_t total_nnz, int64_t nrows, const DBuf& d_jobs,
+                    PlanSlots plan_slots) {
+        const int64_t R = plan_slots(3, 1);
+        const int64_t S = std::min<int64_t>(items, std::max<int64_t>(R * kTuneSamplesPerSlot, 1));
+        PinnedBuf h_s(4 * (size_t)S);
+        int32_t* smp = h_s.as<int32_t>();
+        int32_t q = 0;
+        for (int64_t i = 0; i < S; ++i) {
+            const int64_t k = (int64_t)((__int128)i * items / S);
+            while (q + 1 < nj && jt[q + 1].item_base <= k) ++q;
+            smp[i] = (int32_t)(jt[q].row_base + (jt[q].n - 1 - (k - jt[q].item_base)));
+        }
+        DBuf d_s(4 * (size_t)S), tcnt(64), tjst(sizeof(JobStats) * (size_t)std::max(nj, 1));
+        DBuf t_off(8 * (size_t)std::max<int64_t>(nrows, 1)), t_cnt(4 * (size_t)std::max<int64_t>(nrows, 1)),
+            t_lcnt(4 * (size_t)std::max<int64_t>(nrows, 1));
+        chk(hipMemcpyAsync(d_s.p, h_s.p, 4 * (size_t)S, hipMemcpyHostToDevice, st));
+        DBuf d_rj;
+        if (nj > 1) {
+            d_rj = DBuf(4 * (size_t)std::max<int64_t>(nrows, 1));
+            chk(launch_row_job(d_jobs.as<Job>(), nj, N, d_rj.as<int32_t>(), st));
+        }
+        // scratch output pool for the sample; rows that do not fit are only flagged
+        const int64_t want_pool = pool_estimate(nrows, total_nnz) / std::max<int64_t>(items, 1) * S * 2 + (1 << 20);
+        const int64_t room = (budget - fixed - R * lay.bytes_per_slot) / 4 / 3;
+        const int64_t pcap = std::max<int64_t>(std::min<int64_t>(want_pool, room), 1 << 16);
+        DBuf tpool(4 * (size_t)pcap);
+        EventSet ev;
+        TuneChoice best = kTuneCandidates[0];
+        float best_ms = 0;
+        bool have = false;
+        for (const TuneChoice& c : kTuneCandidates) {
+            const int64_t ns = plan_slots(c.mapping, c.slots_div);
+            auto ss = take_slots(lay, (int32_t)ns, c.mapping == 3 ? 1 : 0, st);
+            TraverseArgs ta{};
+            ta.jobs = d_jobs.as<Job>();
+            ta.njobs = nj;
+            ta.nslots = (int32_t)std::min<int64_t>(ns, ss->nslots);
+            ta.nitems = S;
+            ta.item_rows = d_s.as<int32_t>();
+            ta.row_job = d_rj.as<int32_t>();
+            ta.item_counter = tcnt.as<unsigned long long>();
+            ta.slots = ss->buf.as<uint8_t>();
+            ta.lay = lay;
+            ta.row_off = t_off.as<int64_t>();
+            ta.row_cnt = t_cnt.as<int32_t>();
+            ta.row_lcnt = t_lcnt.as<int32_t>();
+            ta.pool = tpool.as<int32_t>();
+            ta.pool_tail = tcnt.as<unsigned long long>() + 1;
+            ta.pool_cap = pcap;
+            ta.jstats = tjst.as<JobStats>();
+            ta.window = c.window;
+            ta.flags = plan.flags;
+            ta.mapping = c.mapping;
+            chk(launch_zero_i32(tcnt.as<int32_t>(), 16, st));
+            chk(launch_zero_i32(tjst.as<int32_t>(), (int64_t)(sizeof(JobStats) / 4) * nj, st));
+            chk(hipEventRecord(ev[0], st));
+            chk(launch_traverse(ta, st));
+            chk(hipEventRecord(ev[1], st));
+            chk(hipStreamSynchronize(st));
+            give_slots(std::move(ss));
+            float ms = 0;
+            chk(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            if (!have || ms < best_ms * 0.97f) {
+                best = c;
+                best_ms = ms;
+                have = true;
+            }
+        }
+        return best;
     }
 
     int finish_failed(const std::vector<int>& jstat, double t0) {
@@ -893,6 +1311,8 @@ Plan make_plan(const gsofa_opts* o) {
     p.max_super = 128;
     p.flags = 0;
     p.budget = 0;
+    p.window_auto = false;
+    p.allow_trials = true;
     if (o) {
         p.flags = o->flags;
         p.budget = o->mem_budget_bytes;
@@ -914,14 +1334,19 @@ int check_opts(const gsofa_opts* o) {
 
 std::mutex g_api_mu;  // one call at a time per process for the plain entry points
 
-int run_engine(std::vector<MatIn> mats, const gsofa_opts* o, std::vector<gsofa_result*>& outs) {
+int run_engine(std::vector<MatIn> mats, const gsofa_opts* o, std::vector<gsofa_result*>& outs,
+               bool allow_trials = true) {
     Engine eng;
     eng.mats = std::move(mats);
     eng.plan = make_plan(o);
+    eng.plan.allow_trials = allow_trials;
     eng.on_device = o && (o->flags & GSOFA_INPUT_ON_DEVICE);
     eng.st = o ? static_cast<hipStream_t>(o->stream) : nullptr;
     int64_t N = 1;
     for (auto& m : eng.mats) N = std::max<int64_t>(N, m.n);
+    eng.plan.window_auto = eng.plan.window <= 0 && eng.plan.nslots <= 0 &&
+                           (eng.plan.flags & (GSOFA_MAP_WAVE32 | GSOFA_MAP_WG8 | GSOFA_MAP_WG16 |
+                                              GSOFA_LEVEL_ORDER | GSOFA_NO_LINE95)) == 0;
     if (eng.plan.window <= 0) eng.plan.window = auto_window(N);
     if (eng.plan.flags & GSOFA_LEVEL_ORDER) eng.plan.window = (int32_t)std::min<int64_t>(N, 0x7FFFFFFF);
     int rc;
@@ -1047,6 +1472,14 @@ extern "C" GSOFA_API int gsofa_release_cache(void) {
     return GSOFA_OK;
 }
 
+extern "C" GSOFA_API int gsofa_graph_counters(uint64_t* out) {
+    if (!out) return GSOFA_EINVAL;
+    out[0] = g_graph_instantiations.load();
+    out[1] = g_graph_updates.load();
+    out[2] = g_graph_launches.load();
+    return GSOFA_OK;
+}
+
 // ------------------------------------------------------------ the server
 //
 // Continuous batching: max_inflight worker threads, each with its own stream,
@@ -1116,7 +1549,8 @@ void serve_worker(gsofa_server* s, int sid) {
         o.mem_budget_bytes = r.est;
         o.concurrent_sources = serve_slots_for(s, r.n);
         std::vector<gsofa_result*> outs;
-        const int rc = run_engine({MatIn{r.n, r.rp.data(), r.ci.data()}}, &o, outs);
+        // no tuner trials inside a request: they would add to its latency
+        const int rc = run_engine({MatIn{r.n, r.rp.data(), r.ci.data()}}, &o, outs, false);
         gsofa_result* res = (rc == GSOFA_OK && !outs.empty()) ? outs[0] : nullptr;
         if (rc != GSOFA_OK)
             for (auto* x : outs) free_result(x);

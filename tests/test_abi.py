@@ -31,7 +31,7 @@ def g():
 
 def test_exports_every_declared_symbol(g):
     decl = _declared()
-    assert len(decl) == 9 and set(decl) == set(g.EXPORTED)
+    assert len(decl) == 10 and set(decl) == set(g.EXPORTED)
     out = subprocess.run(["nm", "-D", "--defined-only", g.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
     exported = set(re.findall(r" T (gsofa_\w+)", out))
@@ -118,3 +118,10 @@ def test_serve_argument_errors(g):
     out = ctypes.POINTER(g.Result)()
     assert lib.gsofa_serve_poll(None, 1, 0, ctypes.byref(out)) == g.EINVAL
     assert lib.gsofa_serve_close(None) == g.EINVAL
+
+
+def test_graph_counters_argument_error(g):
+    lib = g.load()
+    assert lib.gsofa_graph_counters(None) == g.EINVAL
+    a = g.graph_counters()
+    assert len(a) == 3 and all(x >= 0 for x in a)

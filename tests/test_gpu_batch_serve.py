@@ -167,3 +167,28 @@ def test_serve_many_concurrent_requests(g):
         got = [srv.poll(t, timeout_us=-1) for t in tickets]
     for m, r in zip(mats, got):
         assert same(r, oracle.symbolic(m.n, m.row_ptr, m.col_idx))
+
+
+def test_graph_replays_match_eager(g):
+    """Each phase of a call is captured once, and its executable graph is
+    updated in place for later calls. Every replay, with eager calls and calls
+    of another graph shape in between, gives the eager results."""
+    mats = [synth.batch_member(k) for k in (20, 21, 22, 23)]
+    args = [(m.n, m.row_ptr, m.col_idx) for m in mats]
+    eager = g.batch(args, flags=g.EAGER)
+    for m, r in zip(mats, eager):
+        assert same(r, oracle.symbolic(m.n, m.row_ptr, m.col_idx))
+    c0 = g.graph_counters()
+    for rep in range(4):
+        _say(f"graph replay {rep}")
+        res = g.batch(args)
+        for a, b in zip(res, eager):
+            assert same_result(a, b)
+        again = g.batch(args, flags=g.EAGER)
+        for a, b in zip(again, eager):
+            assert same_result(a, b)
+        one = g.symbolic(*args[rep])
+        assert same_result(one, eager[rep])
+    c1 = g.graph_counters()
+    assert c1[2] > c0[2]
+    assert c1[1] > c0[1]

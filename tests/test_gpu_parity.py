@@ -159,6 +159,7 @@ def test_generator_families(g, idx):
     {"flags": 0x80, "concurrent_sources": 3}, {"flags": 0x100, "window": 1},
     {"flags": 0x80 | 0x10, "window": 64},
     {"window": 253}, {"window": 200, "concurrent_sources": 5}, {"window": 254},
+    {"flags": 0x200}, {"flags": 0x200 | 0x1 | 0x2},
 ], ids=str)
 def test_knobs_do_not_change_results(g, kw):
     m = synth.stencil(27, (11, 10, 9), nd=True, seed=21)
@@ -236,3 +237,20 @@ def test_repeat_calls_are_deterministic(g):
         b = g.symbolic(m.n, m.row_ptr, m.col_idx)
         assert np.array_equal(a.u_idx, b.u_idx) and np.array_equal(a.l_idx, b.l_idx)
         assert np.array_equal(a.supno, b.supno)
+
+
+def test_autotuner_trials_keep_results(g):
+    """Forcing the tuner's trial launches on a mid-size matrix: every candidate
+    runs on a sample of its sources, the fastest is kept, and the result still
+    equals the oracle; a later call of the same class reuses the choice."""
+    m = synth.stencil(27, (22, 21, 20), nd=True, seed=71)
+    ref = run_ref(m.n, m.row_ptr, m.col_idx)
+    _say(f"tuner on n={m.n}")
+    res = g.symbolic(m.n, m.row_ptr, m.col_idx, flags=g.TUNE_NOW)
+    assert res.stats["t_tune_ms"] > 0
+    assert res.stats["mapping"] in (0, 2, 3) and 1 <= res.stats["window"] <= 64
+    assert_same(res, ref)
+    again = g.symbolic(m.n, m.row_ptr, m.col_idx)
+    assert again.stats["t_tune_ms"] == 0
+    assert (again.stats["mapping"], again.stats["window"]) == (res.stats["mapping"], res.stats["window"])
+    assert_same(again, ref)
