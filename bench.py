@@ -61,6 +61,9 @@ def bench_batch(g, torch, synth, reps):
     phases = {k: round(res[0].stats[k], 3) for k in ("t_traverse_ms", "t_emit_ms", "t_supernode_ms",
                                                       "t_total_ms")}
     phases["concurrent_sources"] = res[0].stats["concurrent_sources"]
+    phases["window"] = res[0].stats["window"]
+    phases["mapping"] = res[0].stats["mapping"]
+    phases["t_tune_ms"] = round(res[0].stats["t_tune_ms"], 3)
     for r in res:
         r.free()
     torch.cuda.synchronize()
@@ -71,6 +74,14 @@ def bench_batch(g, torch, synth, reps):
             r.free()
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
+    # the same batch launched kernel by kernel instead of one graph per phase
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = g.batch(dev, flags=flags | g.EAGER, stream=stream)
+        for r in res:
+            r.free()
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / reps
     t0 = time.perf_counter()
     for n, rp, ci in dev:
         r = g.symbolic(n, rp, ci, flags=flags, stream=stream)
@@ -81,6 +92,8 @@ def bench_batch(g, torch, synth, reps):
         f"edges_alg {e_alg:.3e}, phases {phases}")
     return {"matrices": len(mats), "sum_n": int(sum(m.n for m in mats)), "edges_alg": e_alg,
             "ms_per_batch": round(t_batch * 1e3, 3),
+            "eager_ms_per_batch": round(t_eager * 1e3, 3),
+            "graph_counters": list(g.graph_counters()),
             "matrices_per_s": round(len(mats) / t_batch, 1),
             "gteps": round(e_alg / t_batch / 1e9, 3),
             "one_call_per_matrix_ms": round(t_single * 1e3, 3),
