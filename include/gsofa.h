@@ -74,11 +74,13 @@ typedef enum {
 #define GSOFA_LEVEL_ORDER       0x20u /* ablation: the paper's breadth-first frontier
                                          order instead of windowed order; results are
                                          unchanged, work grows                        */
-/* traversal mapping (tuning knob, results unchanged); none set -> one
- * wavefront per source row with one state byte per vertex (windows up to 253) */
+/* traversal mapping (tuning knob, results unchanged); none set -> the
+ * autotuner's choice, by default one wavefront per source row with 32-bit labels */
 #define GSOFA_MAP_WAVE32        0x40u  /* one wavefront per source row, 32-bit labels  */
 #define GSOFA_MAP_WG8           0x80u  /* eight wavefronts per source row              */
 #define GSOFA_MAP_WG16          0x100u /* sixteen wavefronts per source row            */
+#define GSOFA_MAP_BYTE          0x800u /* one wavefront per source row, one state byte
+                                          per vertex (windows up to 253 ids)          */
 /* By default the device work of a call between two host synchronisations
  * (traversal; pointer scans; row sort; supernodes; L transpose and result
  * pointers) is captured into HIP graphs and each phase is one graph launch;
@@ -91,7 +93,7 @@ typedef enum {
  * size class (device, log2 of the largest n, mean row length, batch size) the
  * first call with at least 65,536 source rows times every candidate on one
  * stratified sample of its rows and keeps the fastest for later calls; smaller
- * calls of an untuned class use window 16 with byte states. GSOFA_TUNE_NOW
+ * calls of an untuned class use window 16 with 32-bit labels. GSOFA_TUNE_NOW
  * times the candidates in this call whatever its size, and re-tunes its class.
  * Results are identical for every choice. */
 #define GSOFA_TUNE_NOW          0x400u
@@ -119,9 +121,9 @@ typedef struct {
     double t_supernode_ms;
     double t_total_ms;          /* whole call, host copies included                       */
     int32_t window;             /* threshold-window span used                             */
-    int32_t mapping;            /* traversal mapping used: 3 one wavefront per source with
-                                   byte states, 0 the same with 32-bit labels, 2 / 1 eight /
-                                   sixteen wavefronts per source                          */
+    int32_t mapping;            /* traversal mapping used: 0 one wavefront per source with
+                                   32-bit labels, 3 one wavefront with byte states, 2 / 1
+                                   eight / sixteen wavefronts per source                  */
     double t_tune_ms;           /* autotuner trial time spent in this call (0 if none)    */
 } gsofa_stats;
 

@@ -29,6 +29,7 @@ MAP_WAVE32 = 0x40
 MAP_WG8 = 0x80
 MAP_WG16 = 0x100
 EAGER = 0x200
+MAP_BYTE = 0x800
 TUNE_NOW = 0x400
 
 EXPORTED = ["gsofa_symbolic", "gsofa_batch", "gsofa_serve_open", "gsofa_serve_submit",

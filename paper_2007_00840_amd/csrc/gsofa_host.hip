@@ -50,11 +50,21 @@ struct Status {
 // stream per thread; t_stream names it.
 
 thread_local hipStream_t t_stream = nullptr;
+// Set once a call has synchronised with t_stream for the last time: buffers
+// released after that point need no completion event.
+thread_local bool t_idle = false;
 
 struct StreamScope {
     hipStream_t prev;
-    explicit StreamScope(hipStream_t s) : prev(t_stream) { t_stream = s; }
-    ~StreamScope() { t_stream = prev; }
+    bool prev_idle;
+    explicit StreamScope(hipStream_t s) : prev(t_stream), prev_idle(t_idle) {
+        t_stream = s;
+        t_idle = false;
+    }
+    ~StreamScope() {
+        t_stream = prev;
+        t_idle = prev_idle;
+    }
 };
 
 void drop_idle_slots();
@@ -171,21 +181,76 @@ struct DBuf {
     }
     ~DBuf() { reset(); }
     void reset() {
-        if (p) cache().free(p, st, synced);
+        if (p) cache().free(p, st, synced || (t_idle && st == t_stream));
         p = nullptr;
     }
     template <typename T>
     T* as() const { return static_cast<T*>(p); }
 };
 
-// Pinned host memory for small device-to-host reads inside a call.
+// Pinned host memory for uploads, staging and small reads inside a call,
+// pooled across calls (pinning pages is slow). A block goes back to the pool
+// only once its call's stream is idle; on an error path the release waits for
+// the stream first.
+class PinnedPool {
+   public:
+    void* take(size_t bytes) {
+        bytes = (bytes + 4095) & ~size_t(4095);
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            auto it = free_.lower_bound(bytes);
+            if (it != free_.end() && it->first <= bytes * 2 + (1u << 20)) {
+                void* p = it->second;
+                size_[p] = it->first;
+                pooled_ -= it->first;
+                free_.erase(it);
+                return p;
+            }
+        }
+        void* p = nullptr;
+        chk(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+        std::lock_guard<std::mutex> g(mu_);
+        size_[p] = bytes;
+        return p;
+    }
+    void give(void* p) {
+        if (!t_idle) {
+            (void)hipStreamSynchronize(t_stream);
+            (void)hipGetLastError();
+        }
+        std::lock_guard<std::mutex> g(mu_);
+        auto it = size_.find(p);
+        if (it == size_.end()) return;
+        const size_t b = it->second;
+        size_.erase(it);
+        // keep at most 512 MiB pinned between calls
+        if (pooled_ + b > (512ull << 20)) {
+            (void)hipHostFree(p);
+            return;
+        }
+        free_.emplace(b, p);
+        pooled_ += b;
+    }
+
+   private:
+    std::mutex mu_;
+    std::multimap<size_t, void*> free_;
+    std::unordered_map<void*, size_t> size_;
+    size_t pooled_ = 0;
+};
+
+PinnedPool& pinned_pool() {
+    static PinnedPool* p = new PinnedPool();  // lives until process end
+    return *p;
+}
+
 struct PinnedBuf {
     void* p = nullptr;
-    explicit PinnedBuf(size_t b) { chk(hipHostMalloc(&p, std::max<size_t>(b, 8), hipHostMallocDefault)); }
+    explicit PinnedBuf(size_t b) : p(pinned_pool().take(std::max<size_t>(b, 8))) {}
     PinnedBuf(const PinnedBuf&) = delete;
     PinnedBuf& operator=(const PinnedBuf&) = delete;
     ~PinnedBuf() {
-        if (p) (void)hipHostFree(p);
+        if (p) pinned_pool().give(p);
     }
     template <typename T>
     T* as() const { return static_cast<T*>(p); }
@@ -424,9 +489,19 @@ DeviceInfo device_info() {
     DeviceInfo d;
     int dev = 0;
     chk(hipGetDevice(&dev));
-    hipDeviceProp_t p;
-    chk(hipGetDeviceProperties(&p, dev));
-    d.cus = p.multiProcessorCount;
+    // compute-unit counts per device, queried once
+    static std::mutex mu;
+    static std::map<int, int> cus;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cus.find(dev);
+        if (it != cus.end()) d.cus = it->second;
+        else {
+            int c = 0;
+            chk(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
+            cus[dev] = d.cus = c;
+        }
+    }
     chk(hipMemGetInfo(&d.free_b, &d.total_b));
     return d;
 }
@@ -496,19 +571,22 @@ struct Plan {
     bool allow_trials;  // the tuner may time trial launches in this call
 };
 
-// Traversal mapping. One wavefront per source is the default: per-source
-// frontiers are small (a window holds a few dozen vertices), so a workgroup per
-// source leaves most of its wavefronts idle and was 3-5x slower on the 64^3
-// and 1000^2 stencils. The workgroup variants stay available as tuning knobs.
-// Byte states (mapping 3) need windows of at most 253 ids and keep no label
-// for vertices already in the structure, so the paper's order (window = n) and
-// the line-9.5-off ablation run on 32-bit labels (mapping 0).
+// Traversal mapping. One wavefront per source with 32-bit labels is the
+// default: per-source frontiers are small (a window holds a few dozen
+// vertices), so a workgroup per source leaves most of its wavefronts idle and
+// was 3-5x slower on the 64^3 and 1000^2 stencils, and byte states were 1.5x
+// slower on the 64^3 stencil (byte updates need compare-and-swap loops). The
+// others stay available as tuning knobs and tuner candidates. Byte states
+// (mapping 3) need windows of at most 253 ids and keep no label for vertices
+// already in the structure, so the paper's order (window = n) and the
+// line-9.5-off ablation always run on 32-bit labels.
 int choose_mapping(uint32_t flags, int32_t window) {
     if (flags & GSOFA_MAP_WG16) return 1;
     if (flags & GSOFA_MAP_WG8) return 2;
     if (flags & GSOFA_MAP_WAVE32) return 0;
-    if (window > 253 || (flags & (GSOFA_NO_LINE95 | GSOFA_LEVEL_ORDER))) return 0;
-    return 3;
+    const bool ablation = window > 253 || (flags & (GSOFA_NO_LINE95 | GSOFA_LEVEL_ORDER));
+    if ((flags & GSOFA_MAP_BYTE) && !ablation) return 3;
+    return 0;
 }
 
 int32_t auto_window(int64_t N) {
@@ -521,12 +599,15 @@ int32_t auto_window(int64_t N) {
 
 // ------------------------------------------------------------ autotuner
 //
-// Window span, traversal mapping and the number of sources in flight change
-// only the speed, never the result. For a size class that has not been seen
-// yet (device, log2 of the largest n, mean row length, batch size) and a call
-// with enough sources, the tuner times every candidate on the same stratified
-// sample of the call's sources (8 per slot), keeps the fastest, and reuses it
-// for later calls of the class. Smaller calls use the defaults.
+// Window span and traversal mapping change only the speed, never the result.
+// For a size class that has not been seen yet (device, log2 of the largest n,
+// mean row length, batch size) and a call with enough sources, the tuner times
+// every candidate on the same stratified sample of the call's sources (8 per
+// slot), keeps the fastest, and reuses it for later calls of the class.
+// Smaller calls use the defaults. The number of sources in flight is not tuned:
+// on a sample a few sources per slot long, fewer slots win by balancing the
+// tail better, while at full size they were twice as slow, so every candidate
+// runs on all resident wavefronts.
 
 struct TuneKey {
     int cus, n_log2, deg_bucket, batch_log2;
@@ -536,13 +617,12 @@ struct TuneKey {
 };
 
 struct TuneChoice {
-    int mapping;     // 3 byte states, 0 32-bit labels, 2 eight wavefronts per source
+    int mapping;     // 0 32-bit labels, 3 byte states, 2 eight wavefronts per source
     int32_t window;  // threshold-window span
-    int slots_div;   // sources in flight = resident wavefronts / slots_div
 };
 
 constexpr TuneChoice kTuneCandidates[] = {
-    {3, 16, 1}, {3, 8, 1}, {3, 32, 1}, {3, 64, 1}, {3, 16, 2}, {3, 16, 4}, {0, 16, 1}, {2, 16, 1},
+    {0, 16}, {0, 8}, {0, 32}, {0, 64}, {3, 16}, {2, 16},
 };
 constexpr int64_t kTuneMinSources = 65536;  // calls with fewer sources use the defaults
 constexpr int kTuneSamplesPerSlot = 8;
@@ -674,9 +754,8 @@ struct Engine {
             in_ci = DBuf(4 * (size_t)std::max<int64_t>(ci_tot, 1));
             // pack through a pinned staging buffer
             const size_t stage_b = 4 * (size_t)(rp_tot + ci_tot);
-            void* stage = nullptr;
-            chk(hipHostMalloc(&stage, std::max<size_t>(stage_b, 4), hipHostMallocDefault));
-            int32_t* sp = static_cast<int32_t*>(stage);
+            PinnedBuf stage(std::max<size_t>(stage_b, 4));
+            int32_t* sp = stage.as<int32_t>();
             for (int32_t j = 0; j < nj; ++j) {
                 if (mats[j].n > 0) {
                     std::memcpy(sp + rp_off[j], mats[j].rp, 4 * (size_t)(mats[j].n + 1));
@@ -689,7 +768,6 @@ struct Engine {
             if (ci_tot > 0)
                 chk(hipMemcpyAsync(in_ci.p, sp + rp_tot, 4 * (size_t)ci_tot, hipMemcpyHostToDevice, st));
             chk(hipStreamSynchronize(st));
-            (void)hipHostFree(stage);
             for (int32_t j = 0; j < nj; ++j) {
                 jobs[j].row_ptr = in_rp.as<int32_t>() + rp_off[j];
                 jobs[j].col_idx = in_ci.as<int32_t>() + ci_off[j];
@@ -739,9 +817,9 @@ struct Engine {
         if (budget < fixed + lay.bytes_per_slot) throw Status{GSOFA_ENOMEM};
         const int64_t slot_fit = std::max<int64_t>((budget - fixed) / 2 / lay.bytes_per_slot, 1);
         // sources in flight for a mapping: the resident wavefronts (or blocks),
-        // divided by div, within half of the memory left after the fixed part
-        auto plan_slots = [&](int map, int div) {
-            int64_t want = plan.nslots > 0 ? plan.nslots : (int64_t)traverse_resident_slots(di.cus, map) / div;
+        // within half of the memory left after the fixed part
+        auto plan_slots = [&](int map) {
+            int64_t want = plan.nslots > 0 ? plan.nslots : (int64_t)traverse_resident_slots(di.cus, map);
             want = std::min<int64_t>(want, std::max<int64_t>(items, 1));
             int64_t ns = std::max<int64_t>(std::min<int64_t>(want, slot_fit), 1);
             // the one-wavefront mappings launch whole blocks of 4 wavefronts
@@ -749,7 +827,6 @@ struct Engine {
             return ns;
         };
         int mapping = choose_mapping(plan.flags, plan.window);
-        int slots_div = 1;
         double t_tune = 0;
         if (plan.window_auto) {
             const TuneKey key{di.cus, ceil_log2(N), ceil_log2(std::max<int64_t>(total_nnz * 4 / std::max<int64_t>(nrows, 1), 1)),
@@ -761,7 +838,6 @@ struct Engine {
                 if (it != tune_table().end()) {
                     mapping = it->second.mapping;
                     plan.window = it->second.window;
-                    slots_div = it->second.slots_div;
                     found = true;
                 }
             }
@@ -772,12 +848,11 @@ struct Engine {
                 t_tune = now_ms() - tt0;
                 mapping = c.mapping;
                 plan.window = c.window;
-                slots_div = c.slots_div;
                 std::lock_guard<std::mutex> lk(g_tune_mu);
                 tune_table()[key] = c;
             }
         }
-        const int64_t nslots = plan_slots(mapping, slots_div);
+        const int64_t nslots = plan_slots(mapping);
 
         int64_t pool_cap = pool_estimate(nrows, total_nnz);
         const int64_t pool_room = (budget - fixed - nslots * lay.bytes_per_slot) / 4 / 3;
@@ -1122,6 +1197,8 @@ struct Engine {
         } else {
             keep = std::make_shared<std::vector<DBuf>>();
         }
+        // no more device work in this call: buffers released from here on are idle
+        t_idle = true;
 
         static int32_t zero_xsup = 0;
         for (int32_t j = 0; j < nj; ++j) {
@@ -1211,7 +1288,7 @@ struct Engine {
     TuneChoice tune(const std::vector<Job>& jt, int32_t nj, int64_t N, int64_t items, const SlotLayout& lay,
                     int64_t budget, int64_t fixed, int64_t total_nnz, int64_t nrows, const DBuf& d_jobs,
                     PlanSlots plan_slots) {
-        const int64_t R = plan_slots(3, 1);
+        const int64_t R = plan_slots(0);
         const int64_t S = std::min<int64_t>(items, std::max<int64_t>(R * kTuneSamplesPerSlot, 1));
         PinnedBuf h_s(4 * (size_t)S);
         int32_t* smp = h_s.as<int32_t>();
@@ -1240,7 +1317,7 @@ struct Engine {
         float best_ms = 0;
         bool have = false;
         for (const TuneChoice& c : kTuneCandidates) {
-            const int64_t ns = plan_slots(c.mapping, c.slots_div);
+            const int64_t ns = plan_slots(c.mapping);
             auto ss = take_slots(lay, (int32_t)ns, c.mapping == 3 ? 1 : 0, st);
             TraverseArgs ta{};
             ta.jobs = d_jobs.as<Job>();
@@ -1345,7 +1422,7 @@ int run_engine(std::vector<MatIn> mats, const gsofa_opts* o, std::vector<gsofa_r
     int64_t N = 1;
     for (auto& m : eng.mats) N = std::max<int64_t>(N, m.n);
     eng.plan.window_auto = eng.plan.window <= 0 && eng.plan.nslots <= 0 &&
-                           (eng.plan.flags & (GSOFA_MAP_WAVE32 | GSOFA_MAP_WG8 | GSOFA_MAP_WG16 |
+                           (eng.plan.flags & (GSOFA_MAP_WAVE32 | GSOFA_MAP_WG8 | GSOFA_MAP_WG16 | GSOFA_MAP_BYTE |
                                               GSOFA_LEVEL_ORDER | GSOFA_NO_LINE95)) == 0;
     if (eng.plan.window <= 0) eng.plan.window = auto_window(N);
     if (eng.plan.flags & GSOFA_LEVEL_ORDER) eng.plan.window = (int32_t)std::min<int64_t>(N, 0x7FFFFFFF);

@@ -16,21 +16,22 @@
 // in windows of increasing keys: take the pending vertices with ids in
 // [lo, lo + window), relax breadth-first inside the window until no key in it
 // changes, then move on. A vertex finished in an earlier window can never
-// improve again, so it is marked settled in a bitmap that answers most edge
-// checks with one bit instead of a label. With window = n this is the paper's
-// breadth-first order.
+// improve again. With window = n this is the paper's breadth-first order.
 //
 // One wavefront owns one source slot at a time and pulls sources from a
 // global counter (largest ids first: their work grows with the id, Design
 // Challenges, challenge 2). Frontier compaction uses wavefront ballots and
 // lane prefix counts; per-slot state lives in HBM:
 //   lab   : label per vertex, value-range encoded per source so nothing is
-//           reset between sources (Section 4, maxId initialisation paragraph)
-//   V     : settled bitmap (in-structure vertices and finished windows)
+//           reset between sources (Section 4, maxId initialisation paragraph);
+//           the byte-state kernel keeps one state byte per vertex there
 //   P     : pending bitmap of structure vertices waiting for their window
-//   qa/qb : current / next worklist, qs: per-level dedup stamps
-//   touch : reached vertices outside the structure (settled per window)
+//   qa/qb : current / next worklist (bit 31 of an entry: first visit of the
+//           vertex by this source), qs: per-level dedup stamps
+//   touch : reached vertices outside the structure (byte-state kernel: reset
+//           list)
 //   rowb  : the source row's structure, copied to the output pool at the end
+#include <atomic>
 #include "gsofa_internal.h"
 #include "gsofa.h"
 
@@ -247,7 +248,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t label_rsrc(uint32_t* lab, int6
 //   base + x, x < v               -> v is in the structure (x = 0: original entry)
 //   base + x, x > v               -> reached through intermediates up to x, not (yet) a fill
 // For w > s the first atomic minimum that finds a stale word marks the U entry.
-__global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
+// The label is read first and the atomic minimum is issued only where it can
+// lower it (an atomic on every edge instead measured 4x slower).
+// Six wavefronts per SIMD: the register budget (at most 80 VGPRs) fits without
+// spills and gives 20 % more loads in flight than the unconstrained five.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_traverse(TraverseArgs a) {
     __shared__ WaveTile tiles[kTravWaves];
     __shared__ unsigned long long pushed[kTravWaves][1 << kHashBits];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -426,9 +431,12 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
                 for (int32_t c0 = 0; c0 < qn; c0 += 64) {
                     const int32_t i = c0 + ln;
                     const bool act = i < qn;
-                    const int32_t f = ld_coherent(&cur[act ? i : 0]);
+                    // bit 31 of a queue entry: first visit of the vertex by this source
+                    const int32_t fr = ld_coherent(&cur[act ? i : 0]);
+                    const int32_t f = fr & 0x7FFFFFFF;
                     const int32_t fs = rp[f];
                     const int32_t deg = act ? rp[f + 1] - fs : 0;
+                    if (fr < 0) e_alg += (unsigned long long)deg;
                     const uint32_t dl = dec(ld_coherent(&lab[f]));
                     const uint32_t ov = (dl == kInf) ? kInf : max(dl, (uint32_t)f);
                     e_gpu += (unsigned long long)deg;
@@ -484,11 +492,6 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
                                 }
                             }
                         }
-                        // vertices reached for the first time contribute their degree
-                        int32_t fdeg[kIlp];
-#pragma unroll
-                        for (int kk = 0; kk < kIlp; ++kk)
-                            fdeg[kk] = first[kk] ? rp[w[kk] + 1] - rp[w[kk]] : 0;
                         // drop repeated pushes of a vertex within one level
                         bool evict = false;
 #pragma unroll
@@ -508,10 +511,14 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
                                 if (push[kk]) push[kk] = wg_xchg(&qs[w[kk]], lvl) != lvl;
                         }
                         exact = exact || __ballot(evict) != 0ull;
+                        // a vertex reached for the first time contributes its degree
+                        // once: a pushed one carries the first-visit flag to its
+                        // expansion, where the degree is loaded anyway; the rest (in
+                        // the structure beyond the window) load it here
                         bool any = false;
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
-                            e_alg += (unsigned long long)fdeg[kk];
+                            if (first[kk] && !push[kk]) e_alg += (unsigned long long)(rp[w[kk] + 1] - rp[w[kk]]);
                             any |= emit[kk] | push[kk];
                         }
                         if (__ballot(any) == 0ull) return;
@@ -522,7 +529,9 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
                             rcount += __popcll(m);
                             lcount += __popcll(__ballot(isl[kk]));
                             m = __ballot(push[kk]);
-                            if (push[kk]) nxt[nq + (int32_t)lanes_below(m)] = w[kk];
+                            if (push[kk])
+                                nxt[nq + (int32_t)lanes_below(m)] =
+                                    (int32_t)((uint32_t)w[kk] | (first[kk] ? 0x80000000u : 0u));
                             nq += __popcll(m);
                         }
                     };
@@ -792,9 +801,12 @@ __global__ __launch_bounds__(256) void k_traverse8(TraverseArgs a) {
                 for (int32_t c0 = 0; c0 < qn; c0 += 64) {
                     const int32_t i = c0 + ln;
                     const bool act = i < qn;
-                    const int32_t f = ld_coherent(&cur[act ? i : 0]);
+                    // bit 31 of a queue entry: first visit of the vertex by this source
+                    const int32_t fr = ld_coherent(&cur[act ? i : 0]);
+                    const int32_t f = fr & 0x7FFFFFFF;
                     const int32_t fs = rp[f];
                     const int32_t deg = act ? rp[f + 1] - fs : 0;
+                    if (fr < 0) e_alg += (unsigned long long)deg;
                     const uint32_t fb = (ld_coherent(&stw[f >> 2]) >> ((f & 3) * 8)) & 0xFFu;
                     // a frontier is in the structure (passes its id) or reached in this window
                     const uint32_t ov = fb == kStStruct ? (uint32_t)f
@@ -881,10 +893,6 @@ __global__ __launch_bounds__(256) void k_traverse8(TraverseArgs a) {
                                 tch[kk] = ob[kk] == kStNone;
                             }
                         }
-                        int32_t fdeg[kIlp];
-#pragma unroll
-                        for (int kk = 0; kk < kIlp; ++kk)
-                            fdeg[kk] = first[kk] ? rp[w[kk] + 1] - rp[w[kk]] : 0;
                         bool evict = false;
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
@@ -903,10 +911,11 @@ __global__ __launch_bounds__(256) void k_traverse8(TraverseArgs a) {
                                 if (push[kk]) push[kk] = wg_xchg(&qs[w[kk]], lvl) != lvl;
                         }
                         exact = exact || __ballot(evict) != 0ull;
+                        // first visits: degree counted at expansion (flagged push) or here
                         bool any = false;
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
-                            e_alg += (unsigned long long)fdeg[kk];
+                            if (first[kk] && !push[kk]) e_alg += (unsigned long long)(rp[w[kk] + 1] - rp[w[kk]]);
                             any |= emit[kk] | push[kk] | tch[kk];
                         }
                         if (__ballot(any) == 0ull) return;
@@ -917,7 +926,9 @@ __global__ __launch_bounds__(256) void k_traverse8(TraverseArgs a) {
                             rcount += __popcll(m);
                             lcount += __popcll(__ballot(isl[kk]));
                             m = __ballot(push[kk]);
-                            if (push[kk]) nxt[nq + (int32_t)lanes_below(m)] = w[kk];
+                            if (push[kk])
+                                nxt[nq + (int32_t)lanes_below(m)] =
+                                    (int32_t)((uint32_t)w[kk] | (first[kk] ? 0x80000000u : 0u));
                             nq += __popcll(m);
                             m = __ballot(tch[kk]);
                             if (tch[kk]) touch[tcount + (int32_t)lanes_below(m)] = w[kk];
@@ -1428,6 +1439,12 @@ __global__ __launch_bounds__(64 * NW) void k_traverse_wg(TraverseArgs a) {
 }
 
 int32_t traverse_resident_slots(int cus, int mapping) {
+    // resident blocks per CU, queried once per mapping
+    static std::atomic<int> known[4] = {{-1}, {-1}, {-1}, {-1}};
+    if (mapping >= 0 && mapping < 4) {
+        const int b = known[mapping].load();
+        if (b > 0) return b * ((mapping == 0 || mapping == 3) ? kTravWaves : 1) * cus;
+    }
     int blocks = 0;
     hipError_t e;
     if (mapping == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse8, 64 * kTravWaves, 0);
@@ -1437,6 +1454,8 @@ int32_t traverse_resident_slots(int cus, int mapping) {
     if (e != hipSuccess || blocks <= 0) {
         (void)hipGetLastError();
         blocks = 1;
+    } else if (mapping >= 0 && mapping < 4) {
+        known[mapping].store(blocks);
     }
     return blocks * ((mapping == 0 || mapping == 3) ? kTravWaves : 1) * cus;
 }

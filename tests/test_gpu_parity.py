@@ -110,7 +110,7 @@ def test_edge_sizes(g):
     assert r.nnz_u == n and r.nnz_l == 0 and r.nsuper == n and r.fills == 0
 
 
-@pytest.mark.parametrize("mapping", [0x40, 0x80, 0x100])
+@pytest.mark.parametrize("mapping", [0x40, 0x80, 0x100, 0x800])
 @pytest.mark.parametrize("name", ["dense", "arrow_first", "arrow_last", "tril", "triu"])
 def test_closed_forms_on_gpu(g, name, mapping):
     n = 300
@@ -160,6 +160,9 @@ def test_generator_families(g, idx):
     {"flags": 0x80 | 0x10, "window": 64},
     {"window": 253}, {"window": 200, "concurrent_sources": 5}, {"window": 254},
     {"flags": 0x200}, {"flags": 0x200 | 0x1 | 0x2},
+    {"flags": 0x800}, {"flags": 0x800, "window": 1}, {"flags": 0x800, "window": 3},
+    {"flags": 0x800, "window": 253}, {"flags": 0x800, "window": 200, "concurrent_sources": 5},
+    {"flags": 0x800 | 0x20}, {"flags": 0x800 | 0x10},
 ], ids=str)
 def test_knobs_do_not_change_results(g, kw):
     m = synth.stencil(27, (11, 10, 9), nd=True, seed=21)
