@@ -561,6 +561,9 @@ struct MatIn {
     const int32_t* ci;
 };
 
+// Calls with fewer sources are latency-bound and use the defaults untuned.
+constexpr int64_t kTuneMinSources = 65536;
+
 struct Plan {
     int32_t window;
     int32_t nslots;
@@ -589,12 +592,14 @@ int choose_mapping(uint32_t flags, int32_t window) {
     return 0;
 }
 
-int32_t auto_window(int64_t N) {
+int32_t auto_window(int64_t sources) {
     // Window span for the traversal schedule. Small spans keep revisits low,
-    // wider ones give fuller wavefronts; 16 was the best measured trade-off on
-    // 2D and 3D stencils in nested-dissection order.
-    (void)N;
-    return 16;
+    // wider ones need fewer levels. A call with many sources is bound by
+    // throughput, and 16 was best on the 64^3 and 1000^2 stencils and on the
+    // 4,096-matrix batch; a call with few sources is bound by the latency of
+    // its longest source, and 64 was best for single matrices of a few
+    // thousand rows (2.3 ms against 3.4 ms at 16).
+    return sources >= kTuneMinSources ? 16 : 64;
 }
 
 // ------------------------------------------------------------ autotuner
@@ -617,15 +622,14 @@ struct TuneKey {
 };
 
 struct TuneChoice {
-    int mapping;     // 0 32-bit labels, 3 byte states, 2 eight wavefronts per source
+    int mapping;     // 0 32-bit labels, 3 byte states
     int32_t window;  // threshold-window span
 };
 
 constexpr TuneChoice kTuneCandidates[] = {
-    {0, 16}, {0, 8}, {0, 32}, {0, 64}, {3, 16}, {2, 16},
+    {0, 16}, {0, 32}, {0, 64}, {0, 8}, {3, 16},
 };
-constexpr int64_t kTuneMinSources = 65536;  // calls with fewer sources use the defaults
-constexpr int kTuneSamplesPerSlot = 8;
+constexpr int kTuneSamplesPerSlot = 24;
 
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneChoice>& tune_table() {
@@ -1281,7 +1285,7 @@ struct Engine {
 
     // Times every tuner candidate on one stratified sample of the call's
     // sources (largest ids first inside each matrix, as in the real order) and
-    // returns the fastest; a candidate must beat the current best by 3% to
+    // returns the fastest; a candidate must beat the current best by 5% to
     // replace it, so near-ties keep the earlier (default) one. The sample's
     // rows go to scratch arrays; the slot sets are left clean for the real run.
     template <typename PlanSlots>
@@ -1348,7 +1352,7 @@ struct Engine {
             give_slots(std::move(ss));
             float ms = 0;
             chk(hipEventElapsedTime(&ms, ev[0], ev[1]));
-            if (!have || ms < best_ms * 0.97f) {
+            if (!have || ms < best_ms * 0.95f) {
                 best = c;
                 best_ms = ms;
                 have = true;
@@ -1419,12 +1423,15 @@ int run_engine(std::vector<MatIn> mats, const gsofa_opts* o, std::vector<gsofa_r
     eng.plan.allow_trials = allow_trials;
     eng.on_device = o && (o->flags & GSOFA_INPUT_ON_DEVICE);
     eng.st = o ? static_cast<hipStream_t>(o->stream) : nullptr;
-    int64_t N = 1;
-    for (auto& m : eng.mats) N = std::max<int64_t>(N, m.n);
+    int64_t N = 1, rows = 0;
+    for (auto& m : eng.mats) {
+        N = std::max<int64_t>(N, m.n);
+        rows += std::max<int32_t>(m.n, 0);
+    }
     eng.plan.window_auto = eng.plan.window <= 0 && eng.plan.nslots <= 0 &&
                            (eng.plan.flags & (GSOFA_MAP_WAVE32 | GSOFA_MAP_WG8 | GSOFA_MAP_WG16 | GSOFA_MAP_BYTE |
                                               GSOFA_LEVEL_ORDER | GSOFA_NO_LINE95)) == 0;
-    if (eng.plan.window <= 0) eng.plan.window = auto_window(N);
+    if (eng.plan.window <= 0) eng.plan.window = auto_window(rows);
     if (eng.plan.flags & GSOFA_LEVEL_ORDER) eng.plan.window = (int32_t)std::min<int64_t>(N, 0x7FFFFFFF);
     int rc;
     try {

@@ -1576,9 +1576,15 @@ hipError_t launch_scan_counts(const int32_t* a, const int32_t* b, int64_t n, int
 // A segment holds distinct int32 values. Sorted ascending, its first `split`
 // values go to outA and the rest to outB.
 
-constexpr int kSmallSeg = 256;     // one wavefront, LDS bitonic
-constexpr int kBigSeg = 16384;     // one block, LDS bitonic
-constexpr int kBitmapBits = 1 << 19;  // 64 KB LDS bitmap per pass
+// Segment sorts. Every segment holds distinct non-negative ids, so where its
+// values span few ids it is ranked in an LDS bitmap (set a bit per value, count
+// bits per word, prefix-sum, emit in order): work ~ span/32 + cnt instead of a
+// bitonic network's cnt log^2 cnt. One wavefront takes a segment whose span
+// fits its 8192-bit bitmap, or a wide one of at most 256 values (bitonic);
+// the rest go to a block that ranks them in 64 KB bitmap chunks.
+constexpr int kSmallSeg = 256;                 // wavefront bitonic limit
+constexpr int kWaveBmWords = kSmallSeg;        // wavefront bitmap: the same LDS, 8192 bits
+constexpr int kBitmapBits = 1 << 19;           // block bitmap chunk: 64 KB of LDS
 
 __device__ __forceinline__ void write_split(int32_t idx, int32_t v, int32_t split, int32_t* outA,
                                             int32_t* outB) {
@@ -1587,8 +1593,8 @@ __device__ __forceinline__ void write_split(int32_t idx, int32_t v, int32_t spli
 }
 
 // wavefront bitonic sort of up to 256 values in LDS buffer buf[256]
-__device__ void wave_sort_segment(const int32_t* in, int32_t cnt, int32_t split, int32_t* outA,
-                                  int32_t* outB, int32_t* buf) {
+__device__ void wave_bitonic_segment(const int32_t* in, int32_t cnt, int32_t split, int32_t* outA,
+                                     int32_t* outB, int32_t* buf) {
     const int ln = lane_id();
     int32_t m = 1;
     while (m < cnt) m <<= 1;
@@ -1614,72 +1620,104 @@ __device__ void wave_sort_segment(const int32_t* in, int32_t cnt, int32_t split,
     wave_fence();
 }
 
-// block bitonic sort of up to kBigSeg values; falls back to bitmap ranking
-// for longer segments (values distinct and >= 0).
-__device__ void block_sort_segment(const int32_t* in, int32_t cnt, int32_t split, int32_t* outA,
-                                   int32_t* outB, int32_t* buf /* kBigSeg ints = 64 KB */) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    if (cnt <= kBigSeg) {
-        int32_t m = 1;
-        while (m < cnt) m <<= 1;
-        for (int i = tid; i < m; i += nt) buf[i] = i < cnt ? in[i] : 0x7FFFFFFF;
-        __syncthreads();
-        for (int32_t k = 2; k <= m; k <<= 1) {
-            for (int32_t jj = k >> 1; jj > 0; jj >>= 1) {
-                for (int32_t i = tid; i < m; i += nt) {
-                    const int32_t ixj = i ^ jj;
-                    if (ixj > i) {
-                        const int32_t x = buf[i], y = buf[ixj];
-                        const bool up = (i & k) == 0;
-                        if ((x > y) == up) {
-                            buf[i] = y;
-                            buf[ixj] = x;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        for (int i = tid; i < cnt; i += nt) write_split(i, buf[i], split, outA, outB);
-        __syncthreads();
-        return;
+// wavefront bitmap ranking of a segment with values in [lo, lo + 32 * words)
+__device__ void wave_bitmap_segment(const int32_t* in, int32_t cnt, int32_t lo, int32_t words, int32_t split,
+                                    int32_t* outA, int32_t* outB, uint32_t* bm) {
+    const int ln = lane_id();
+    for (int i = ln; i < words; i += 64) bm[i] = 0u;
+    wave_fence();
+    for (int i = ln; i < cnt; i += 64) {
+        const int32_t d = in[i] - lo;
+        atomicOr(&bm[d >> 5], 1u << (d & 31));
     }
-    // bitmap ranking over value chunks of kBitmapBits
+    wave_fence();
+    // lane ln owns words [ln * per, ln * per + per)
+    const int per = (words + 63) >> 6;
+    int32_t mine = 0;
+    for (int q = 0; q < per; ++q) {
+        const int i = ln * per + q;
+        if (i < words) mine += __popc(bm[i]);
+    }
+    int32_t r = wave_incl_scan(mine) - mine;
+    for (int q = 0; q < per; ++q) {
+        const int i = ln * per + q;
+        uint32_t word = i < words ? bm[i] : 0u;
+        while (word) {
+            const int b = __builtin_ctz(word);
+            word &= word - 1u;
+            write_split(r++, lo + i * 32 + b, split, outA, outB);
+        }
+    }
+    wave_fence();
+}
+
+// One wavefront sorts the segment if it can (bitmap for a narrow span,
+// bitonic for at most 256 values); returns false if the segment needs a block.
+__device__ bool wave_sort_segment(const int32_t* in, int32_t cnt, int32_t split, int32_t* outA, int32_t* outB,
+                                  int32_t* buf) {
+    if (cnt <= 0) return true;
+    int32_t vmin = 0x7FFFFFFF, vmax = -1;
+    for (int i = lane_id(); i < cnt; i += 64) {
+        const int32_t v = in[i];
+        vmin = min(vmin, v);
+        vmax = max(vmax, v);
+    }
+    vmin = wave_min(vmin);
+    vmax = wave_max(vmax);
+    const int64_t span = (int64_t)vmax - vmin + 1;
+    if (span <= 32 * kWaveBmWords) {
+        wave_bitmap_segment(in, cnt, vmin, (int32_t)((span + 31) >> 5), split, outA, outB, (uint32_t*)buf);
+        return true;
+    }
+    if (cnt <= kSmallSeg) {
+        wave_bitonic_segment(in, cnt, split, outA, outB, buf);
+        return true;
+    }
+    return false;
+}
+
+// block bitmap ranking over value chunks of at most kBitmapBits
+__device__ void block_sort_segment(const int32_t* in, int32_t cnt, int32_t split, int32_t* outA,
+                                   int32_t* outB, uint32_t* bm /* kBitmapBits / 32 words */) {
     __shared__ int32_t red[2];
     __shared__ int32_t wsum[16];
-    uint32_t* bm = (uint32_t*)buf;
+    const int tid = threadIdx.x, nt = blockDim.x;
     int32_t vmin = 0x7FFFFFFF, vmax = -1;
     for (int i = tid; i < cnt; i += nt) {
         const int32_t v = in[i];
         vmin = min(vmin, v);
         vmax = max(vmax, v);
     }
-    if (tid == 0) { red[0] = 0x7FFFFFFF; red[1] = -1; }
+    if (tid == 0) {
+        red[0] = 0x7FFFFFFF;
+        red[1] = -1;
+    }
     __syncthreads();
     atomicMin(&red[0], vmin);
     atomicMax(&red[1], vmax);
     __syncthreads();
     vmin = red[0];
     vmax = red[1];
+    __syncthreads();
     int32_t rank_base = 0;
-    const int nwords = kBitmapBits / 32;
-    const int per_t = nwords / nt;  // words per thread (nt divides nwords)
     for (int64_t c0 = vmin; c0 <= vmax; c0 += kBitmapBits) {
+        const int64_t bits = std::min<int64_t>((int64_t)vmax - c0 + 1, kBitmapBits);
+        const int nwords = (int)((bits + 31) >> 5);
+        const int per_t = (nwords + nt - 1) / nt;  // words per thread
         for (int i = tid; i < nwords; i += nt) bm[i] = 0u;
         __syncthreads();
         for (int i = tid; i < cnt; i += nt) {
             const int64_t d = (int64_t)in[i] - c0;
-            if (d >= 0 && d < kBitmapBits) atomicOr(&bm[d >> 5], 1u << (d & 31));
+            if (d >= 0 && d < bits) atomicOr(&bm[d >> 5], 1u << (d & 31));
         }
         __syncthreads();
         // each thread owns per_t consecutive words: count, block scan, emit
         int32_t mine = 0;
-        for (int q = 0; q < per_t; ++q) mine += __popc(bm[tid * per_t + q]);
-        int32_t x = mine;
-        for (int d = 1; d < 64; d <<= 1) {
-            int32_t t = __shfl_up(x, (unsigned)d, 64);
-            if (lane_id() >= d) x += t;
+        for (int q = 0; q < per_t; ++q) {
+            const int i = tid * per_t + q;
+            if (i < nwords) mine += __popc(bm[i]);
         }
+        const int32_t x = wave_incl_scan(mine);
         if (lane_id() == 63) wsum[tid >> 6] = x;
         __syncthreads();
         int32_t pre = 0, tot = 0;
@@ -1689,12 +1727,12 @@ __device__ void block_sort_segment(const int32_t* in, int32_t cnt, int32_t split
         }
         int32_t r = rank_base + pre + x - mine;
         for (int q = 0; q < per_t; ++q) {
-            uint32_t word = bm[tid * per_t + q];
+            const int i = tid * per_t + q;
+            uint32_t word = i < nwords ? bm[i] : 0u;
             while (word) {
                 const int b = __builtin_ctz(word);
                 word &= word - 1u;
-                const int32_t v = (int32_t)(c0 + (int64_t)(tid * per_t + q) * 32 + b);
-                write_split(r++, v, split, outA, outB);
+                write_split(r++, (int32_t)(c0 + (int64_t)i * 32 + b), split, outA, outB);
             }
         }
         rank_base += tot;
@@ -1713,12 +1751,9 @@ __global__ __launch_bounds__(256) void k_sort_rows_small(int64_t nrows, const in
     const int wv = threadIdx.x >> 6;
     const int64_t r = (int64_t)blockIdx.x * 4 + wv;
     if (r >= nrows) return;
-    const int32_t cnt = row_cnt[r];
-    if (cnt > kSmallSeg) {
+    if (!wave_sort_segment(pool + row_off[r], row_cnt[r], row_lcnt[r], l_idx + l_ptr[r], u_idx + u_ptr[r],
+                           buf[wv]))
         if (lane_id() == 0) big_list[atomicAdd(big_count, 1)] = (int32_t)r;
-        return;
-    }
-    wave_sort_segment(pool + row_off[r], cnt, row_lcnt[r], l_idx + l_ptr[r], u_idx + u_ptr[r], buf[wv]);
 }
 
 __global__ __launch_bounds__(256) void k_sort_rows_big(const int64_t* row_off, const int32_t* row_cnt,
@@ -1726,12 +1761,12 @@ __global__ __launch_bounds__(256) void k_sort_rows_big(const int64_t* row_off, c
                                                        const int64_t* u_ptr, int32_t* u_idx,
                                                        const int64_t* l_ptr, int32_t* l_idx,
                                                        const int32_t* big_list, const int32_t* big_count) {
-    __shared__ int32_t buf[kBigSeg];
+    __shared__ uint32_t bm[kBitmapBits / 32];
     const int32_t nb = *big_count;
     for (int32_t q = blockIdx.x; q < nb; q += gridDim.x) {
         const int32_t r = big_list[q];
         block_sort_segment(pool + row_off[r], row_cnt[r], row_lcnt[r], l_idx + l_ptr[r],
-                           u_idx + u_ptr[r], buf);
+                           u_idx + u_ptr[r], bm);
     }
 }
 
@@ -1785,22 +1820,19 @@ __global__ __launch_bounds__(256) void k_sort_cols_small(int64_t ncols, const in
     const int64_t c = (int64_t)blockIdx.x * 4 + wv;
     if (c >= ncols) return;
     const int32_t cnt = (int32_t)(cptr[c + 1] - cptr[c]);
-    if (cnt > kSmallSeg) {
+    if (!wave_sort_segment(tmp + cptr[c], cnt, cnt, out + cptr[c], nullptr, buf[wv]))
         if (lane_id() == 0) big_list[atomicAdd(big_count, 1)] = (int32_t)c;
-        return;
-    }
-    wave_sort_segment(tmp + cptr[c], cnt, cnt, out + cptr[c], nullptr, buf[wv]);
 }
 
 __global__ __launch_bounds__(256) void k_sort_cols_big(const int64_t* cptr, const int32_t* tmp,
                                                        int32_t* out, const int32_t* big_list,
                                                        const int32_t* big_count) {
-    __shared__ int32_t buf[kBigSeg];
+    __shared__ uint32_t bm[kBitmapBits / 32];
     const int32_t nb = *big_count;
     for (int32_t q = blockIdx.x; q < nb; q += gridDim.x) {
         const int32_t c = big_list[q];
         const int32_t cnt = (int32_t)(cptr[c + 1] - cptr[c]);
-        block_sort_segment(tmp + cptr[c], cnt, cnt, out + cptr[c], nullptr, buf);
+        block_sort_segment(tmp + cptr[c], cnt, cnt, out + cptr[c], nullptr, bm);
     }
 }
 
