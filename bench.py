@@ -30,6 +30,29 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def recorded_traffic(kernel, mapping, window):
+    """HBM bytes per launch of the traversal kernel from the rocprofv3 PMC record
+    in profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings),
+    or None when no record matches this kernel source and configuration."""
+    import hashlib
+    import re
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(here, "paper_2007_00840_amd", "csrc", "gsofa_kernels.hip")
+    rec = os.path.join(here, "profiles", "k_traverse_64cube_27pt.md")
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        text = open(rec).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic-record: kernel=(\S+) source_sha256_16=(\S+) mapping=(\d+) window=(\d+) "
+                  r"fetch_bytes=(\d+) write_bytes=(\d+)", text)
+    if not m or m.group(1) != kernel or m.group(2) != sha:
+        return None
+    if int(m.group(3)) != mapping or int(m.group(4)) != window:
+        return None
+    return int(m.group(5)) + int(m.group(6))
+
+
 def cpu_baseline(m, stride):
     """The oracle (fill2 search, all host threads) on every stride-th row."""
     import numpy as np
@@ -291,7 +314,9 @@ def main():
                    "n": m.n, "nnz": m.nnz, "result": "device-resident L (CSC), U (CSR), supernodes",
                    "max_supernode": 128, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": recorded_traffic(KERNEL_OF_MAPPING.get(stats[-1]["mapping"], "k_traverse"),
+                                                 stats[-1]["mapping"], stats[-1]["window"]),
                      "kernel": KERNEL_OF_MAPPING.get(stats[-1]["mapping"], "k_traverse"),
                      "bytes_per_unit": BYTES_PER_EDGE,
                      "unit_count": e_alg, "kernel_ms": round(t_trav, 3)},
