@@ -125,11 +125,13 @@ def bench_batch(g, torch, synth, reps):
             "phases_ms": phases}
 
 
-def _serve_run(g, synth, trace, cap_s, mode, max_outstanding=64):
-    """Offers the trace on its arrival schedule for cap_s seconds. mode 'serve'
-    uses the continuous-batching server, 'plain' one gsofa_symbolic call at a
-    time in arrival order. Latency = completion - scheduled arrival; requests
-    that arrived before the cap but did not finish count as censored."""
+def _serve_run(g, synth, trace, cap_s, mode, drain_s=0.0, max_inflight=8, max_outstanding=64):
+    """Offers the requests of the trace that arrive within cap_s seconds, on
+    their arrival schedule, and waits up to drain_s more for them to finish.
+    mode 'serve' uses the continuous-batching server, 'plain' one
+    gsofa_symbolic call at a time in arrival order; neither runs tuner trials.
+    Latency = completion - scheduled arrival; requests not finished by
+    cap_s + drain_s count as censored."""
     import threading
     from concurrent.futures import ThreadPoolExecutor
     import numpy as np
@@ -141,12 +143,13 @@ def _serve_run(g, synth, trace, cap_s, mode, max_outstanding=64):
         futs[r.rid] = pool.submit(r.matrix)
     t0 = time.perf_counter()
     nxt = 0
+    end_s = cap_s + drain_s
     if mode == "serve":
-        srv = g.Server(max_inflight=4, mem_budget_bytes=200 << 30)
+        srv = g.Server(max_inflight=max_inflight, mem_budget_bytes=200 << 30)
         outstanding = {}
         while True:
             now = time.perf_counter() - t0
-            if now > cap_s:
+            if now > end_s or len(done_at) == len(arrived):
                 break
             # submit everything that has arrived, within the outstanding bound
             while (nxt < len(arrived) and arrived[nxt].arrival_s <= now
@@ -167,7 +170,7 @@ def _serve_run(g, synth, trace, cap_s, mode, max_outstanding=64):
     else:
         while nxt < len(arrived):
             now = time.perf_counter() - t0
-            if now > cap_s:
+            if now > end_s:
                 break
             r = arrived[nxt]
             if r.arrival_s > now:
@@ -177,7 +180,7 @@ def _serve_run(g, synth, trace, cap_s, mode, max_outstanding=64):
             k = nxt + 2 * max_outstanding
             if k < len(arrived):
                 futs[arrived[k].rid] = pool.submit(arrived[k].matrix)
-            g.symbolic(m.n, m.row_ptr, m.col_idx)
+            g.symbolic(m.n, m.row_ptr, m.col_idx, flags=g.NO_TUNE)
             done_at[r.rid] = time.perf_counter() - t0
             nxt += 1
     pool.shutdown(wait=False, cancel_futures=True)
@@ -185,17 +188,20 @@ def _serve_run(g, synth, trace, cap_s, mode, max_outstanding=64):
     lat.sort()
     def pct(q):
         v = lat[min(len(lat) - 1, int(np.ceil(q * len(lat))) - 1)]
-        return round(float(v) * 1e3, 1) if np.isfinite(v) else f"> {cap_s * 1e3:.0f} (censored)"
+        return round(float(v) * 1e3, 1) if np.isfinite(v) else f"> {end_s * 1e3:.0f} (censored)"
+    span = max(done_at.values()) if done_at else end_s
     return {"offered": len(arrived), "completed": len(done_at),
-            "completed_per_s": round(len(done_at) / cap_s, 2),
+            "completed_per_s": round(len(done_at) / max(span, 1e-9), 2),
             "p50_ms": pct(0.5), "p99_ms": pct(0.99),
             "censored_frac": round(float(np.mean(~np.isfinite(lat))), 4)}
 
 
-def bench_serve(g, synth, cap_s):
-    """The request stream (config 5): Poisson arrivals at 200 requests/s,
-    n log-uniform in [1e3, 1e6], 2D 9-point or 3D 27-point, ND order, drop
-    0.2, memory budget 200 GB; offered for cap_s seconds."""
+def bench_serve(g, synth, cap_s, low_rate):
+    """The request stream: Poisson arrivals at 200 requests/s, n log-uniform
+    in [1e3, 1e6], 2D 9-point or 3D 27-point, ND order, drop 0.2, memory
+    budget 200 GB; offered for cap_s seconds. That rate is far above what one
+    GPU completes, so most latencies are censored; the same request mix at
+    low_rate requests/s, drained to the end, gives the latency distribution."""
     trace = synth.serve_trace()
     log(f"serve: {len(trace)} requests in the 60 s trace; offering the first {cap_s:.0f} s")
     out = {"cap_s": cap_s, "rate_per_s": synth.SERVE_RATE}
@@ -206,6 +212,15 @@ def bench_serve(g, synth, cap_s):
     a = out["continuous_batching"]["completed"]
     b = out["plain_sequential"]["completed"]
     out["throughput_vs_plain"] = round(a / b, 3) if b else None
+    if low_rate > 0:
+        low = synth.serve_trace(rate=low_rate)
+        low_cap = cap_s / 2
+        res = {"rate_per_s": low_rate, "cap_s": low_cap, "drain_s": 3 * low_cap}
+        res["continuous_batching"] = _serve_run(g, synth, low, low_cap, "serve", drain_s=3 * low_cap)
+        log(f"serve at {low_rate}/s: {res['continuous_batching']}")
+        res["plain_sequential"] = _serve_run(g, synth, low, low_cap, "plain", drain_s=3 * low_cap)
+        log(f"serve plain at {low_rate}/s: {res['plain_sequential']}")
+        out["low_rate"] = res
     return out
 
 
@@ -226,6 +241,8 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=3, help="0 = skip the batch measurement")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="wall cap of the request-stream measurement (0 = skip)")
+    ap.add_argument("--serve-low-rate", type=float, default=1.0,
+                    help="requests/s of the drained low-rate request stream (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -289,7 +306,7 @@ def main():
         f"supernode {t_sn:.1f} ms, {gteps:.1f} GTEPS")
 
     batch = bench_batch(g, torch, synth, args.batch_reps) if args.batch_reps > 0 else None
-    serve = bench_serve(g, synth, args.serve_seconds) if args.serve_seconds > 0 else None
+    serve = bench_serve(g, synth, args.serve_seconds, args.serve_low_rate) if args.serve_seconds > 0 else None
 
     base = None
     if args.cpu_stride > 0:

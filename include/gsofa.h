@@ -97,6 +97,9 @@ typedef enum {
  * times the candidates in this call whatever its size, and re-tunes its class.
  * Results are identical for every choice. */
 #define GSOFA_TUNE_NOW          0x400u
+/* Never time tuner trials in this call (latency-sensitive callers): use the size
+ * class's cached choice, else the defaults. The server sets it for every request. */
+#define GSOFA_NO_TUNE           0x2000u
 
 /* A CSR pattern: n rows, row_ptr[n+1], col_idx[row_ptr[n]]; host pointers
  * unless GSOFA_INPUT_ON_DEVICE is set. */

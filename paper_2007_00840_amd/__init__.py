@@ -31,6 +31,7 @@ MAP_WG16 = 0x100
 EAGER = 0x200
 MAP_BYTE = 0x800
 TUNE_NOW = 0x400
+NO_TUNE = 0x2000
 
 EXPORTED = ["gsofa_symbolic", "gsofa_batch", "gsofa_serve_open", "gsofa_serve_submit",
             "gsofa_serve_poll", "gsofa_serve_close", "gsofa_result_free", "gsofa_strerror",

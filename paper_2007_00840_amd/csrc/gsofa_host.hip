@@ -127,6 +127,13 @@ class DevCache {
         free_.emplace(it->second, Blk{p, st, ev});
         used_.erase(it);
     }
+    // bytes held in idle cached blocks (handed back to the device on pressure)
+    size_t idle_bytes() {
+        std::lock_guard<std::mutex> g(mu_);
+        size_t t = 0;
+        for (auto& kv : free_) t += kv.first;
+        return t;
+    }
     void release() {
         std::lock_guard<std::mutex> g(mu_);
         for (auto& kv : free_) {
@@ -437,7 +444,8 @@ std::unique_ptr<SlotSet> take_slots(const SlotLayout& lay, int32_t nslots, int m
         std::lock_guard<std::mutex> g(g_slot_mu);
         auto& v = idle_slots();
         for (size_t i = 0; i < v.size(); ++i) {
-            if (v[i]->lay.N == lay.N && v[i]->nslots >= nslots) {
+            // a set laid out for up to twice the size serves smaller matrices too
+            if (v[i]->lay.N >= lay.N && v[i]->lay.N <= 2 * lay.N && v[i]->nslots >= nslots) {
                 auto s = std::move(v[i]);
                 v.erase(v.begin() + i);
                 s->buf.st = st;
@@ -480,9 +488,17 @@ void drop_idle_slots() {
     drop.swap(idle_slots());
 }
 
+size_t idle_slot_bytes() {
+    std::lock_guard<std::mutex> g(g_slot_mu);
+    size_t t = 0;
+    for (auto& s : idle_slots()) t += s->buf.bytes;
+    return t;
+}
+
 struct DeviceInfo {
     int cus = 256;
     size_t free_b = 0, total_b = 0;
+    size_t reclaimable = 0;  // idle memory this library caches and gives back on demand
 };
 
 DeviceInfo device_info() {
@@ -503,6 +519,7 @@ DeviceInfo device_info() {
         }
     }
     chk(hipMemGetInfo(&d.free_b, &d.total_b));
+    d.reclaimable = cache().idle_bytes() + idle_slot_bytes();
     return d;
 }
 
@@ -816,7 +833,8 @@ struct Engine {
         // ---- plan the concurrent sources
         const SlotLayout lay = slot_layout(N);
         const DeviceInfo di = device_info();
-        int64_t budget = plan.budget > 0 ? plan.budget : (int64_t)(di.free_b * 0.9);
+        // default budget: free device memory plus what this library holds idle
+        int64_t budget = plan.budget > 0 ? plan.budget : (int64_t)((di.free_b + di.reclaimable) * 0.9);
         const int64_t fixed = fixed_bytes(nrows, total_nnz);
         if (budget < fixed + lay.bytes_per_slot) throw Status{GSOFA_ENOMEM};
         const int64_t slot_fit = std::max<int64_t>((budget - fixed) / 2 / lay.bytes_per_slot, 1);
@@ -891,7 +909,7 @@ struct Engine {
         ta.row_job = d_row_job.as<int32_t>();
         ta.item_counter = counters.as<unsigned long long>();
         ta.slots = slots->buf.as<uint8_t>();
-        ta.lay = lay;
+        ta.lay = slots->lay;
         ta.row_off = row_off.as<int64_t>();
         ta.row_cnt = row_cnt.as<int32_t>();
         ta.row_lcnt = row_lcnt.as<int32_t>();
@@ -1332,7 +1350,7 @@ struct Engine {
             ta.row_job = d_rj.as<int32_t>();
             ta.item_counter = tcnt.as<unsigned long long>();
             ta.slots = ss->buf.as<uint8_t>();
-            ta.lay = lay;
+            ta.lay = ss->lay;
             ta.row_off = t_off.as<int64_t>();
             ta.row_cnt = t_cnt.as<int32_t>();
             ta.row_lcnt = t_lcnt.as<int32_t>();
@@ -1420,7 +1438,7 @@ int run_engine(std::vector<MatIn> mats, const gsofa_opts* o, std::vector<gsofa_r
     Engine eng;
     eng.mats = std::move(mats);
     eng.plan = make_plan(o);
-    eng.plan.allow_trials = allow_trials;
+    eng.plan.allow_trials = allow_trials && !(eng.plan.flags & GSOFA_NO_TUNE);
     eng.on_device = o && (o->flags & GSOFA_INPUT_ON_DEVICE);
     eng.st = o ? static_cast<hipStream_t>(o->stream) : nullptr;
     int64_t N = 1, rows = 0;
@@ -1586,6 +1604,7 @@ struct gsofa_server {
         int32_t n;
         std::vector<int32_t> rp, ci;
         int64_t est;
+        int32_t nslots;  // sources in flight for this request
     };
     std::deque<Req> queue;
     int32_t inflight = 0;
@@ -1605,10 +1624,18 @@ int64_t estimate_request_bytes(int32_t n, int64_t nnz, int32_t nslots) {
     return budget_for(n, nnz, nslots, lay);
 }
 
-int32_t serve_slots_for(const gsofa_server* s, int32_t n) {
-    if (s->opts.concurrent_sources > 0) return std::min(s->opts.concurrent_sources, std::max(n, 1));
-    const int32_t per = std::max(s->slots_total / std::max(1, s->max_inflight / 2), 64);
-    return std::min(per, std::max(n, 1));
+// Sources in flight for one request: a share of the resident wavefronts (two
+// requests' kernels fill the device), never more than the request has rows,
+// and few enough that the request's estimate fits the whole budget; 0 if even
+// one source does not fit.
+int32_t serve_slots_for(const gsofa_server* s, int32_t n, int64_t nnz) {
+    int32_t want;
+    if (s->opts.concurrent_sources > 0) want = std::min(s->opts.concurrent_sources, std::max(n, 1));
+    else want = std::min(std::max(s->slots_total / std::max(1, s->max_inflight / 2), 64), std::max(n, 1));
+    const SlotLayout lay = slot_layout(std::max<int64_t>(n, 1));
+    const int64_t rest = s->budget - budget_for(n, nnz, 0, lay);
+    const int64_t fit = rest > 0 ? rest / (2 * lay.bytes_per_slot) : 0;
+    return (int32_t)std::min<int64_t>(want, fit);
 }
 
 void serve_worker(gsofa_server* s, int sid) {
@@ -1631,7 +1658,7 @@ void serve_worker(gsofa_server* s, int sid) {
         o.stream = s->streams[sid];
         o.flags &= ~(uint32_t)GSOFA_INPUT_ON_DEVICE;
         o.mem_budget_bytes = r.est;
-        o.concurrent_sources = serve_slots_for(s, r.n);
+        o.concurrent_sources = r.nslots;
         std::vector<gsofa_result*> outs;
         // no tuner trials inside a request: they would add to its latency
         const int rc = run_engine({MatIn{r.n, r.rp.data(), r.ci.data()}}, &o, outs, false);
@@ -1660,8 +1687,9 @@ extern "C" GSOFA_API int gsofa_serve_open(const gsofa_opts* opts, int32_t max_in
     try {
         (void)hipGetDevice(&s->device);
         DeviceInfo di = device_info();
-        s->slots_total = traverse_resident_slots(di.cus, 3);
-        s->budget = s->opts.mem_budget_bytes > 0 ? s->opts.mem_budget_bytes : (int64_t)(di.free_b * 0.85);
+        s->slots_total = traverse_resident_slots(di.cus, 0);
+        s->budget = s->opts.mem_budget_bytes > 0 ? s->opts.mem_budget_bytes
+                                                 : (int64_t)((di.free_b + di.reclaimable) * 0.85);
         s->streams.assign(s->max_inflight, nullptr);
         for (auto& st : s->streams) chk(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     } catch (...) {
@@ -1693,7 +1721,9 @@ extern "C" GSOFA_API int gsofa_serve_submit(gsofa_server* s, const gsofa_csr* m,
     } catch (const std::bad_alloc&) {
         return GSOFA_ENOMEM;
     }
-    r.est = estimate_request_bytes(m->n, nnz, serve_slots_for(s, m->n));
+    r.nslots = serve_slots_for(s, m->n, nnz);
+    if (r.nslots < 1) return GSOFA_ECAPACITY;
+    r.est = estimate_request_bytes(m->n, nnz, r.nslots);
     std::lock_guard<std::mutex> g(s->mu);
     if (s->closing) return GSOFA_EINVAL;
     if (r.est > s->budget) return GSOFA_ECAPACITY;
