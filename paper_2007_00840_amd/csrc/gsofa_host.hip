@@ -889,8 +889,12 @@ struct Engine {
         DBuf counters(64);  // [0] item counter, [1] pool tail
         DBuf jst(sizeof(JobStats) * std::max(nj, 1));
         DBuf pool(4 * (size_t)pool_cap);
-        DBuf d_row_job;
-        if (nj > 1) d_row_job = DBuf(4 * (size_t)std::max<int64_t>(nrows, 1));
+        DBuf d_row_job, d_item_job;
+        if (nj > 1) {
+            d_row_job = DBuf(4 * (size_t)std::max<int64_t>(nrows, 1));
+            d_item_job = DBuf(4 * (size_t)std::max<int64_t>(nrows, 1));
+        }
+        DBuf row_stats(sizeof(RowStat) * (size_t)std::max<int64_t>(nrows, 1));
         // job statistics and the pool tail come back through pinned memory
         PinnedBuf h_stats(sizeof(JobStats) * (size_t)std::max(nj, 1) + 64);
         JobStats* hst = h_stats.as<JobStats>();
@@ -907,6 +911,8 @@ struct Engine {
         ta.nitems = items;
         ta.item_rows = nullptr;
         ta.row_job = d_row_job.as<int32_t>();
+        ta.item_job = d_item_job.as<int32_t>();
+        ta.row_stats = row_stats.as<RowStat>();
         ta.item_counter = counters.as<unsigned long long>();
         ta.slots = slots->buf.as<uint8_t>();
         ta.lay = slots->lay;
@@ -925,10 +931,14 @@ struct Engine {
             // phase 1: one persistent traversal launch over every source of every matrix
             Phase ph(kPhaseTraverse, graphs, st);
             const hipStream_t s = ph.stream();
-            if (nj > 1) chk(launch_row_job(d_jobs.as<Job>(), nj, N, d_row_job.as<int32_t>(), s));
+            if (nj > 1) {
+                chk(launch_row_job(d_jobs.as<Job>(), nj, N, d_row_job.as<int32_t>(), s));
+                chk(launch_row_job(d_jobs.as<Job>(), nj, N, d_item_job.as<int32_t>(), s, true));
+            }
             chk(launch_zero_i32(counters.as<int32_t>(), 16, s));
             chk(launch_zero_i32(jst.as<int32_t>(), (int64_t)(sizeof(JobStats) / 4) * nj, s));
             chk(launch_traverse(ta, s));
+            chk(launch_job_stats(d_jobs.as<Job>(), nj, row_stats.as<RowStat>(), jst.as<JobStats>(), s));
             chk(hipMemcpyAsync(hst, jst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, s));
             chk(hipMemcpyAsync(h_tail, counters.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, s));
             ph.launch();
@@ -969,8 +979,7 @@ struct Engine {
             ta.nitems = (int64_t)redo.size();
             ta.pool = pool.as<int32_t>();
             ta.pool_cap = new_cap;
-            // stats were already counted for these rows in the first pass: keep a copy
-            std::vector<JobStats> keep(hst, hst + nj);
+            // redone rows store the same per-source statistics again
             chk(launch_zero_i32(jst.as<int32_t>(), (int64_t)(sizeof(JobStats) / 4) * nj, st));
             float first_ms = 0;
             chk(hipEventElapsedTime(&first_ms, ev[0], ev[4]));
@@ -978,18 +987,13 @@ struct Engine {
             chk(hipEventRecord(ev[0], st));
             chk(launch_traverse(ta, st));
             chk(hipEventRecord(ev[4], st));
+            chk(launch_job_stats(d_jobs.as<Job>(), nj, row_stats.as<RowStat>(), jst.as<JobStats>(), st));
             chk(hipMemcpyAsync(hst, jst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, st));
             chk(hipMemcpyAsync(h_tail, counters.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, st));
             chk(hipStreamSynchronize(st));
             for (int32_t q = 0; q < nj; ++q) {
                 if (hst[q].err & kErrOverflow) throw Status{GSOFA_ENOMEM};
                 if (hst[q].err & kErrDuplicate) jstat[ord[q]] = GSOFA_EINVAL;
-                // the first pass already counted the redone rows' edges once
-                hst[q].edges_alg = keep[q].edges_alg;
-                hst[q].edges_gpu = keep[q].edges_gpu;
-                hst[q].iterations = keep[q].iterations;
-                hst[q].windows = keep[q].windows;
-                hst[q].diag = keep[q].diag;
             }
             pool_cap = new_cap;
         }
@@ -1348,6 +1352,8 @@ struct Engine {
             ta.nitems = S;
             ta.item_rows = d_s.as<int32_t>();
             ta.row_job = d_rj.as<int32_t>();
+            ta.item_job = nullptr;
+            ta.row_stats = nullptr;
             ta.item_counter = tcnt.as<unsigned long long>();
             ta.slots = ss->buf.as<uint8_t>();
             ta.lay = ss->lay;

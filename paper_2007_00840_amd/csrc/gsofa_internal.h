@@ -31,6 +31,15 @@ struct JobStats {
     int32_t pad;
 };
 
+// Per-source statistics, stored once per source without atomics and summed
+// per matrix afterwards (k_job_stats).
+struct RowStat {
+    unsigned long long edges_alg;
+    unsigned long long edges_gpu;
+    uint32_t iterations;
+    uint32_t windows;  // bit 31: the row stores its own diagonal entry
+};
+
 constexpr int32_t kErrDuplicate = 1;
 constexpr int32_t kErrOverflow = 2;
 
@@ -52,6 +61,8 @@ struct TraverseArgs {
     int64_t nitems;                   // work items (sources) in total
     const int32_t* item_rows;         // optional explicit list of global rows (re-runs)
     const int32_t* row_job;           // global row -> job (only read with item_rows)
+    const int32_t* item_job;          // work item -> job (nullptr: one job)
+    RowStat* row_stats;               // per global row (nullptr: not recorded)
     unsigned long long* item_counter; // dynamic work distribution
     uint8_t* slots;                   // nslots * bytes_per_slot
     SlotLayout lay;
@@ -82,8 +93,12 @@ hipError_t launch_init_slots(uint8_t* slots, int32_t nslots, SlotLayout lay, hip
 hipError_t launch_traverse(const TraverseArgs& a, hipStream_t st);
 // source slots that fit on the device at once (occupancy of the traversal kernel)
 int32_t traverse_resident_slots(int cus, int mapping);
+// out[base_j + i] = j for i < n_j, base = row_base (by_item false) or item_base
 hipError_t launch_row_job(const Job* jobs_dev, int32_t njobs, int64_t max_n, int32_t* row_job,
-                          hipStream_t st);
+                          hipStream_t st, bool by_item = false);
+// jstats[j] = sums of row_stats over the rows of job j (err is left as it is)
+hipError_t launch_job_stats(const Job* jobs_dev, int32_t njobs, const RowStat* row_stats, JobStats* jstats,
+                            hipStream_t st);
 // out[0..n] = exclusive scan of (a[i] - (b ? b[i] : 0)); scratch >= scan_scratch_elems(n)
 int64_t scan_scratch_elems(int64_t n);
 hipError_t launch_scan_counts(const int32_t* a, const int32_t* b, int64_t n, int64_t* out,

@@ -202,21 +202,58 @@ hipError_t launch_validate(const Job* jobs_dev, int32_t njobs, int64_t max_n, in
     return hipGetLastError();
 }
 
-__global__ void k_row_job(const Job* jobs, int32_t njobs, int32_t* row_job) {
+__global__ void k_row_job(const Job* jobs, int32_t njobs, int32_t* row_job, bool by_item) {
     const int32_t j = blockIdx.y;
     if (j >= njobs) return;
     const Job J = jobs[j];
+    const int64_t base = by_item ? J.item_base : J.row_base;
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < J.n;
          r += (int64_t)gridDim.x * blockDim.x)
-        row_job[J.row_base + r] = j;
+        row_job[base + r] = j;
 }
 
 hipError_t launch_row_job(const Job* jobs_dev, int32_t njobs, int64_t max_n, int32_t* row_job,
-                          hipStream_t st) {
+                          hipStream_t st, bool by_item) {
     if (njobs <= 0) return hipSuccess;
     int gx = (int)std::min<int64_t>((max_n + 255) / 256, 1024);
     if (gx < 1) gx = 1;
-    hipLaunchKernelGGL(k_row_job, dim3(gx, njobs), dim3(256), 0, st, jobs_dev, njobs, row_job);
+    hipLaunchKernelGGL(k_row_job, dim3(gx, njobs), dim3(256), 0, st, jobs_dev, njobs, row_job, by_item);
+    return hipGetLastError();
+}
+
+// One wavefront per job sums the per-source statistics of its rows.
+__global__ __launch_bounds__(64) void k_job_stats(const Job* jobs, int32_t njobs, const RowStat* rs,
+                                                  JobStats* js) {
+    const int32_t j = blockIdx.x;
+    if (j >= njobs) return;
+    const Job J = jobs[j];
+    unsigned long long ea = 0, eg = 0, it = 0, wn = 0, dg = 0;
+    for (int64_t r = threadIdx.x; r < J.n; r += 64) {
+        const RowStat x = rs[J.row_base + r];
+        ea += x.edges_alg;
+        eg += x.edges_gpu;
+        it += x.iterations;
+        wn += x.windows & 0x7FFFFFFFu;
+        dg += x.windows >> 31;
+    }
+    ea = wave_sum_u64(ea);
+    eg = wave_sum_u64(eg);
+    it = wave_sum_u64(it);
+    wn = wave_sum_u64(wn);
+    dg = wave_sum_u64(dg);
+    if (threadIdx.x == 0) {
+        js[j].edges_alg = ea;
+        js[j].edges_gpu = eg;
+        js[j].iterations = it;
+        js[j].windows = wn;
+        js[j].diag = dg;
+    }
+}
+
+hipError_t launch_job_stats(const Job* jobs_dev, int32_t njobs, const RowStat* row_stats, JobStats* jstats,
+                            hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_job_stats, dim3(njobs), dim3(64), 0, st, jobs_dev, njobs, row_stats, jstats);
     return hipGetLastError();
 }
 
@@ -292,13 +329,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
             j = a.row_job ? a.row_job[gr] : 0;
             s = (int32_t)(gr - a.jobs[j].row_base);
         } else {
-            int32_t lo = 0, hi = a.njobs - 1;
-            while (lo < hi) {
-                int32_t mid = (lo + hi + 1) >> 1;
-                if (a.jobs[mid].item_base <= (int64_t)k) lo = mid;
-                else hi = mid - 1;
+            if (a.item_job) {
+                j = a.item_job[k];
+            } else {
+                int32_t lo = 0, hi = a.njobs - 1;
+                while (lo < hi) {
+                    int32_t mid = (lo + hi + 1) >> 1;
+                    if (a.jobs[mid].item_base <= (int64_t)k) lo = mid;
+                    else hi = mid - 1;
+                }
+                j = lo;
             }
-            j = lo;
             s = a.jobs[j].n - 1 - (int32_t)((int64_t)k - a.jobs[j].item_base);
         }
         j = __builtin_amdgcn_readfirstlane(j);
@@ -608,13 +649,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 
         e_alg = wave_sum_u64(e_alg);
         e_gpu = wave_sum_u64(e_gpu);
-        if (ln == 0) {
-            atomicAdd(&a.jstats[j].edges_alg, e_alg);
-            atomicAdd(&a.jstats[j].edges_gpu, e_gpu);
-            atomicAdd(&a.jstats[j].iterations, (unsigned long long)n_iter);
-            atomicAdd(&a.jstats[j].windows, (unsigned long long)n_win);
-            if (ndiag > 0) atomicAdd(&a.jstats[j].diag, 1ull);
-        }
+        if (ln == 0 && a.row_stats)
+            a.row_stats[grow] = RowStat{e_alg, e_gpu, n_iter, (n_win & 0x7FFFFFFFu) | (ndiag > 0 ? 0x80000000u : 0u)};
         slot_fence();
     }
     if (ln == 0) {
@@ -678,13 +714,17 @@ __global__ __launch_bounds__(256) void k_traverse8(TraverseArgs a) {
             j = a.row_job ? a.row_job[gr] : 0;
             s = (int32_t)(gr - a.jobs[j].row_base);
         } else {
-            int32_t lo = 0, hi = a.njobs - 1;
-            while (lo < hi) {
-                int32_t mid = (lo + hi + 1) >> 1;
-                if (a.jobs[mid].item_base <= (int64_t)k) lo = mid;
-                else hi = mid - 1;
+            if (a.item_job) {
+                j = a.item_job[k];
+            } else {
+                int32_t lo = 0, hi = a.njobs - 1;
+                while (lo < hi) {
+                    int32_t mid = (lo + hi + 1) >> 1;
+                    if (a.jobs[mid].item_base <= (int64_t)k) lo = mid;
+                    else hi = mid - 1;
+                }
+                j = lo;
             }
-            j = lo;
             s = a.jobs[j].n - 1 - (int32_t)((int64_t)k - a.jobs[j].item_base);
         }
         j = __builtin_amdgcn_readfirstlane(j);
@@ -1029,13 +1069,8 @@ __global__ __launch_bounds__(256) void k_traverse8(TraverseArgs a) {
 
         e_alg = wave_sum_u64(e_alg);
         e_gpu = wave_sum_u64(e_gpu);
-        if (ln == 0) {
-            atomicAdd(&a.jstats[j].edges_alg, e_alg);
-            atomicAdd(&a.jstats[j].edges_gpu, e_gpu);
-            atomicAdd(&a.jstats[j].iterations, (unsigned long long)n_iter);
-            atomicAdd(&a.jstats[j].windows, (unsigned long long)n_win);
-            if (ndiag > 0) atomicAdd(&a.jstats[j].diag, 1ull);
-        }
+        if (ln == 0 && a.row_stats)
+            a.row_stats[grow] = RowStat{e_alg, e_gpu, n_iter, (n_win & 0x7FFFFFFFu) | (ndiag > 0 ? 0x80000000u : 0u)};
         slot_fence();
     }
     if (ln == 0) meta[1] = lvl;
@@ -1108,13 +1143,17 @@ __global__ __launch_bounds__(64 * NW) void k_traverse_wg(TraverseArgs a) {
                     j = a.row_job ? a.row_job[gr] : 0;
                     s = (int32_t)(gr - a.jobs[j].row_base);
                 } else {
-                    int32_t lo = 0, hi = a.njobs - 1;
-                    while (lo < hi) {
-                        int32_t mid = (lo + hi + 1) >> 1;
-                        if (a.jobs[mid].item_base <= (int64_t)k) lo = mid;
-                        else hi = mid - 1;
+                    if (a.item_job) {
+                        j = a.item_job[k];
+                    } else {
+                        int32_t lo = 0, hi = a.njobs - 1;
+                        while (lo < hi) {
+                            int32_t mid = (lo + hi + 1) >> 1;
+                            if (a.jobs[mid].item_base <= (int64_t)k) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        j = lo;
                     }
-                    j = lo;
                     s = a.jobs[j].n - 1 - (int32_t)((int64_t)k - a.jobs[j].item_base);
                 }
             }
@@ -1424,11 +1463,9 @@ __global__ __launch_bounds__(64 * NW) void k_traverse_wg(TraverseArgs a) {
             a.row_cnt[grow] = rc;
             a.row_lcnt[grow] = C.lcount;
             if (!fits) atomicOr(&a.jstats[j].err, kErrOverflow);
-            atomicAdd(&a.jstats[j].edges_alg, C.e_alg);
-            atomicAdd(&a.jstats[j].edges_gpu, C.e_gpu);
-            atomicAdd(&a.jstats[j].iterations, (unsigned long long)n_iter);
-            atomicAdd(&a.jstats[j].windows, (unsigned long long)n_win);
-            if (C.ndiag > 0) atomicAdd(&a.jstats[j].diag, 1ull);
+            if (a.row_stats)
+                a.row_stats[grow] = RowStat{C.e_alg, C.e_gpu, n_iter,
+                                            (n_win & 0x7FFFFFFFu) | (C.ndiag > 0 ? 0x80000000u : 0u)};
         }
         __syncthreads();
     }
