@@ -125,6 +125,42 @@ def bench_batch(g, torch, synth, reps):
             "phases_ms": phases}
 
 
+def bench_2d(g, torch, synth, steps):
+    """The 2D workload (9-point stencil on a 1000 x 1000 grid, nested
+    dissection, drop 0.2): one warm-up call (tunes its size class), then
+    `steps` timed calls, inputs and results in device memory."""
+    m = synth.config(2)
+    log(f"2d: {m.desc} n={m.n} nnz={m.nnz}")
+    rp = torch.from_numpy(m.row_ptr).cuda()
+    ci = torch.from_numpy(m.col_idx).cuda()
+    stream = torch.cuda.current_stream().cuda_stream
+    r = g.symbolic(m.n, rp, ci, flags=g.RESULT_ON_DEVICE, stream=stream)
+    tune_ms = r.stats["t_tune_ms"]
+    r.free()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = g.symbolic(m.n, rp, ci, flags=g.RESULT_ON_DEVICE, stream=stream)
+        stats.append(r.stats)
+        fills = r.fills
+        r.free()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    e_alg = stats[-1]["edges_alg"]
+    t_trav = sum(x["t_traverse_ms"] for x in stats) / steps
+    out = {"workload": "2D 9-point stencil 1000x1000, nested dissection, drop 0.2, seed 2",
+           "n": m.n, "nnz": m.nnz, "ms_per_call": round(ms, 3), "gteps": round(e_alg / ms / 1e6, 3),
+           "edges_alg": e_alg, "fills": fills, "t_traverse_ms": round(t_trav, 3),
+           "traverse_algorithmic_gbs": round(BYTES_PER_EDGE * e_alg / t_trav / 1e6, 1),
+           "traverse_frac_of_hbm_peak": round(BYTES_PER_EDGE * e_alg / t_trav / 1e6 / HBM_PEAK_GBS, 4),
+           "t_emit_ms": round(sum(x["t_emit_ms"] for x in stats) / steps, 3),
+           "window": stats[-1]["window"], "mapping": stats[-1]["mapping"],
+           "concurrent_sources": stats[-1]["concurrent_sources"], "t_tune_ms_warmup": round(tune_ms, 3)}
+    log(f"2d: {out}")
+    return out
+
+
 def _serve_run(g, synth, trace, cap_s, mode, drain_s=0.0, max_inflight=8, max_outstanding=64):
     """Offers the requests of the trace that arrive within cap_s seconds, on
     their arrival schedule, and waits up to drain_s more for them to finish.
@@ -238,6 +274,7 @@ def main():
     ap.add_argument("--window", type=int, default=0)
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--flags", type=int, default=0)
+    ap.add_argument("--twod-steps", type=int, default=2, help="timed calls on the 2D workload (0 = skip)")
     ap.add_argument("--batch-reps", type=int, default=3, help="0 = skip the batch measurement")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="wall cap of the request-stream measurement (0 = skip)")
@@ -305,6 +342,8 @@ def main():
     log(f"steps: {ms:.1f} ms/step, traverse {t_trav:.1f} ms, emit {t_emit:.1f} ms, "
         f"supernode {t_sn:.1f} ms, {gteps:.1f} GTEPS")
 
+    twod = bench_2d(g, torch, synth, args.twod_steps) if args.twod_steps > 0 else None
+    g.release_cache()  # the 2D workload's slot sets are not reused below
     batch = bench_batch(g, torch, synth, args.batch_reps) if args.batch_reps > 0 else None
     serve = bench_serve(g, synth, args.serve_seconds, args.serve_low_rate) if args.serve_seconds > 0 else None
 
@@ -348,6 +387,7 @@ def main():
         "concurrent_sources": stats[-1]["concurrent_sources"],
         "window": stats[-1]["window"], "mapping": stats[-1]["mapping"],
         "t_tune_ms_warmup": round(max(s["t_tune_ms"] for s in warm_stats), 3) if warm_stats else 0.0,
+        "workload_2d": twod,
         "batch": batch,
         "serve": serve,
     }
