@@ -1653,10 +1653,18 @@ int32_t serve_slots_for(const gsofa_server* s, int32_t n, int64_t nnz) {
     return (int32_t)std::min<int64_t>(want, fit);
 }
 
+// Requests of at most kServeSmallRows rows admitted together share one engine
+// call: one persistent traversal launch over all their sources, as in
+// gsofa_batch. Larger requests run alone (their own launch fills the device).
+constexpr int32_t kServeSmallRows = 65536;
+constexpr size_t kServeMaxGroup = 64;
+constexpr int64_t kServeGroupRows = 1 << 20;
+
 void serve_worker(gsofa_server* s, int sid) {
     (void)hipSetDevice(s->device);
     for (;;) {
-        gsofa_server::Req r;
+        std::vector<gsofa_server::Req> grp;
+        int64_t grp_est = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv.wait(lk, [&] {
@@ -1664,26 +1672,50 @@ void serve_worker(gsofa_server* s, int sid) {
                 return s->mem_in_use + s->queue.front().est <= s->budget;
             });
             if (s->queue.empty()) return;  // closing and drained
-            r = std::move(s->queue.front());
+            grp.push_back(std::move(s->queue.front()));
             s->queue.pop_front();
+            grp_est = grp[0].est;
+            if (grp[0].n <= kServeSmallRows) {
+                // later small requests that fit the memory budget join, in arrival order
+                int64_t rows = grp[0].n;
+                for (auto it = s->queue.begin(); it != s->queue.end() && grp.size() < kServeMaxGroup;) {
+                    if (it->n <= kServeSmallRows && rows + it->n <= kServeGroupRows &&
+                        s->mem_in_use + grp_est + it->est <= s->budget) {
+                        rows += it->n;
+                        grp_est += it->est;
+                        grp.push_back(std::move(*it));
+                        it = s->queue.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+            }
             s->inflight++;
-            s->mem_in_use += r.est;
+            s->mem_in_use += grp_est;
         }
         gsofa_opts o = s->opts;
         o.stream = s->streams[sid];
         o.flags &= ~(uint32_t)GSOFA_INPUT_ON_DEVICE;
-        o.mem_budget_bytes = r.est;
-        o.concurrent_sources = r.nslots;
+        o.mem_budget_bytes = grp_est;
+        // a lone request keeps its planned share of sources; a group plans from its budget
+        o.concurrent_sources = grp.size() == 1 ? grp[0].nslots : 0;
+        std::vector<MatIn> mats;
+        for (auto& r : grp) mats.push_back(MatIn{r.n, r.rp.data(), r.ci.data()});
         std::vector<gsofa_result*> outs;
         // no tuner trials inside a request: they would add to its latency
-        const int rc = run_engine({MatIn{r.n, r.rp.data(), r.ci.data()}}, &o, outs, false);
-        gsofa_result* res = (rc == GSOFA_OK && !outs.empty()) ? outs[0] : nullptr;
-        if (rc != GSOFA_OK)
-            for (auto* x : outs) free_result(x);
+        const int rc = run_engine(std::move(mats), &o, outs, false);
         std::lock_guard<std::mutex> g(s->mu);
-        s->done[r.ticket] = {rc, res};
+        for (size_t i = 0; i < grp.size(); ++i) {
+            gsofa_result* res = i < outs.size() ? outs[i] : nullptr;
+            int st = res ? res->stats.status : (rc != GSOFA_OK ? rc : GSOFA_EDEVICE);
+            if (res && st != GSOFA_OK) {
+                free_result(res);
+                res = nullptr;
+            }
+            s->done[grp[i].ticket] = {st, res};
+        }
         s->inflight--;
-        s->mem_in_use -= r.est;
+        s->mem_in_use -= grp_est;
         s->cv.notify_all();
     }
 }

@@ -192,3 +192,17 @@ def test_graph_replays_match_eager(g):
     c1 = g.graph_counters()
     assert c1[2] > c0[2]
     assert c1[1] > c0[1]
+
+
+def test_serve_groups_many_small_requests(g):
+    """Many small requests queued at once share launches (a worker takes the
+    queued small requests that fit its budget together); every result must
+    still equal the oracle's, also with a large request among them."""
+    mats = [synth.batch_member(200 + k) for k in range(60)]
+    mats.insert(30, synth.stencil(27, (30, 29, 28), nd=True, seed=301))
+    _say(f"serve grouping: {len(mats)} requests")
+    with g.Server(max_inflight=3) as srv:
+        tickets = [srv.submit(m.n, m.row_ptr, m.col_idx) for m in mats]
+        got = [srv.poll(t, timeout_us=-1) for t in tickets]
+    for m, r in zip(mats, got):
+        assert same(r, oracle.symbolic(m.n, m.row_ptr, m.col_idx))
