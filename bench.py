@@ -30,27 +30,38 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def recorded_traffic(kernel, mapping, window):
+TRAVERSAL_SOURCE_END = b"// ------------------------------------------------- byte-state variant"
+
+
+def traversal_source_hash():
+    """SHA-256 (16 hex digits) of the kernel source up to the byte-state
+    section: the helpers and k_traverse, which the PMC record describes."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = open(os.path.join(here, "paper_2007_00840_amd", "csrc", "gsofa_kernels.hip"), "rb").read()
+    end = src.find(TRAVERSAL_SOURCE_END)
+    return hashlib.sha256(src[:end] if end >= 0 else src).hexdigest()[:16]
+
+
+def recorded_traffic(kernel, mapping, window, sources):
     """HBM bytes per launch of the traversal kernel from the rocprofv3 PMC record
     in profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings),
     or None when no record matches this kernel source and configuration."""
-    import hashlib
     import re
     here = os.path.dirname(os.path.abspath(__file__))
-    src = os.path.join(here, "paper_2007_00840_amd", "csrc", "gsofa_kernels.hip")
     rec = os.path.join(here, "profiles", "k_traverse_64cube_27pt.md")
     try:
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        sha = traversal_source_hash()
         text = open(rec).read()
     except OSError:
         return None
     m = re.search(r"traffic-record: kernel=(\S+) source_sha256_16=(\S+) mapping=(\d+) window=(\d+) "
-                  r"fetch_bytes=(\d+) write_bytes=(\d+)", text)
+                  r"sources=(\d+) fetch_bytes=(\d+) write_bytes=(\d+)", text)
     if not m or m.group(1) != kernel or m.group(2) != sha:
         return None
-    if int(m.group(3)) != mapping or int(m.group(4)) != window:
+    if int(m.group(3)) != mapping or int(m.group(4)) != window or int(m.group(5)) != sources:
         return None
-    return int(m.group(5)) + int(m.group(6))
+    return int(m.group(6)) + int(m.group(7))
 
 
 def cpu_baseline(m, stride):
@@ -372,7 +383,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": recorded_traffic(KERNEL_OF_MAPPING.get(stats[-1]["mapping"], "k_traverse"),
-                                                 stats[-1]["mapping"], stats[-1]["window"]),
+                                                 stats[-1]["mapping"], stats[-1]["window"],
+                                                 stats[-1]["concurrent_sources"]),
                      "kernel": KERNEL_OF_MAPPING.get(stats[-1]["mapping"], "k_traverse"),
                      "bytes_per_unit": BYTES_PER_EDGE,
                      "unit_count": e_alg, "kernel_ms": round(t_trav, 3)},

@@ -947,7 +947,7 @@ struct Engine {
             chk(launch_zero_i32(counters.as<int32_t>(), 16, s));
             chk(launch_zero_i32(jst.as<int32_t>(), (int64_t)(sizeof(JobStats) / 4) * nj, s));
             chk(launch_traverse(ta, s));
-            chk(launch_job_stats(d_jobs.as<Job>(), nj, row_stats.as<RowStat>(), jst.as<JobStats>(), s));
+            chk(launch_job_stats(d_jobs.as<Job>(), nj, N, row_stats.as<RowStat>(), jst.as<JobStats>(), s));
             chk(hipMemcpyAsync(hst, jst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, s));
             chk(hipMemcpyAsync(h_tail, counters.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, s));
             ph.launch();
@@ -996,7 +996,7 @@ struct Engine {
             chk(hipEventRecord(ev[0], st));
             chk(launch_traverse(ta, st));
             chk(hipEventRecord(ev[4], st));
-            chk(launch_job_stats(d_jobs.as<Job>(), nj, row_stats.as<RowStat>(), jst.as<JobStats>(), st));
+            chk(launch_job_stats(d_jobs.as<Job>(), nj, N, row_stats.as<RowStat>(), jst.as<JobStats>(), st));
             chk(hipMemcpyAsync(hst, jst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, st));
             chk(hipMemcpyAsync(h_tail, counters.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, st));
             chk(hipStreamSynchronize(st));

@@ -96,9 +96,10 @@ int32_t traverse_resident_slots(int cus, int mapping);
 // out[base_j + i] = j for i < n_j, base = row_base (by_item false) or item_base
 hipError_t launch_row_job(const Job* jobs_dev, int32_t njobs, int64_t max_n, int32_t* row_job,
                           hipStream_t st, bool by_item = false);
-// jstats[j] = sums of row_stats over the rows of job j (err is left as it is)
-hipError_t launch_job_stats(const Job* jobs_dev, int32_t njobs, const RowStat* row_stats, JobStats* jstats,
-                            hipStream_t st);
+// jstats[j] += sums of row_stats over the rows of job j (err is left as it is);
+// jstats must be zero beforehand
+hipError_t launch_job_stats(const Job* jobs_dev, int32_t njobs, int64_t max_n, const RowStat* row_stats,
+                            JobStats* jstats, hipStream_t st);
 // out[0..n] = exclusive scan of (a[i] - (b ? b[i] : 0)); scratch >= scan_scratch_elems(n)
 int64_t scan_scratch_elems(int64_t n);
 hipError_t launch_scan_counts(const int32_t* a, const int32_t* b, int64_t n, int64_t* out,

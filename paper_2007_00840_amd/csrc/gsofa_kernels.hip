@@ -221,42 +221,6 @@ hipError_t launch_row_job(const Job* jobs_dev, int32_t njobs, int64_t max_n, int
     return hipGetLastError();
 }
 
-// One wavefront per job sums the per-source statistics of its rows.
-__global__ __launch_bounds__(64) void k_job_stats(const Job* jobs, int32_t njobs, const RowStat* rs,
-                                                  JobStats* js) {
-    const int32_t j = blockIdx.x;
-    if (j >= njobs) return;
-    const Job J = jobs[j];
-    unsigned long long ea = 0, eg = 0, it = 0, wn = 0, dg = 0;
-    for (int64_t r = threadIdx.x; r < J.n; r += 64) {
-        const RowStat x = rs[J.row_base + r];
-        ea += x.edges_alg;
-        eg += x.edges_gpu;
-        it += x.iterations;
-        wn += x.windows & 0x7FFFFFFFu;
-        dg += x.windows >> 31;
-    }
-    ea = wave_sum_u64(ea);
-    eg = wave_sum_u64(eg);
-    it = wave_sum_u64(it);
-    wn = wave_sum_u64(wn);
-    dg = wave_sum_u64(dg);
-    if (threadIdx.x == 0) {
-        js[j].edges_alg = ea;
-        js[j].edges_gpu = eg;
-        js[j].iterations = it;
-        js[j].windows = wn;
-        js[j].diag = dg;
-    }
-}
-
-hipError_t launch_job_stats(const Job* jobs_dev, int32_t njobs, const RowStat* row_stats, JobStats* jstats,
-                            hipStream_t st) {
-    if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_job_stats, dim3(njobs), dim3(64), 0, st, jobs_dev, njobs, row_stats, jstats);
-    return hipGetLastError();
-}
-
 // -------------------------------------------------------------- traversal
 
 struct WaveTile {
@@ -1510,6 +1474,59 @@ hipError_t launch_traverse(const TraverseArgs& a, hipStream_t st) {
         const int blocks = (a.nslots + kTravWaves - 1) / kTravWaves;
         hipLaunchKernelGGL(k_traverse, dim3(blocks), dim3(64 * kTravWaves), 0, st, a);
     }
+    return hipGetLastError();
+}
+
+// Per-job sums of the per-source statistics: blocks of 256 rows of one job
+// each add their partial sums (jstats starts zeroed; err is left as it is).
+__global__ __launch_bounds__(256) void k_job_stats(const Job* jobs, int32_t njobs, const RowStat* rs,
+                                                   JobStats* js) {
+    __shared__ unsigned long long part[5][4];
+    const int32_t j = blockIdx.y;
+    if (j >= njobs) return;
+    const Job J = jobs[j];
+    unsigned long long ea = 0, eg = 0, it = 0, wn = 0, dg = 0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < J.n; r += (int64_t)gridDim.x * blockDim.x) {
+        const RowStat x = rs[J.row_base + r];
+        ea += x.edges_alg;
+        eg += x.edges_gpu;
+        it += x.iterations;
+        wn += x.windows & 0x7FFFFFFFu;
+        dg += x.windows >> 31;
+    }
+    ea = wave_sum_u64(ea);
+    eg = wave_sum_u64(eg);
+    it = wave_sum_u64(it);
+    wn = wave_sum_u64(wn);
+    dg = wave_sum_u64(dg);
+    const int wv = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        part[0][wv] = ea;
+        part[1][wv] = eg;
+        part[2][wv] = it;
+        part[3][wv] = wn;
+        part[4][wv] = dg;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const unsigned long long v = part[threadIdx.x][0] + part[threadIdx.x][1] + part[threadIdx.x][2] +
+                                     part[threadIdx.x][3];
+        if (v) {
+            unsigned long long* f = threadIdx.x == 0 ? &js[j].edges_alg
+                                    : threadIdx.x == 1 ? &js[j].edges_gpu
+                                    : threadIdx.x == 2 ? &js[j].iterations
+                                    : threadIdx.x == 3 ? &js[j].windows
+                                                       : &js[j].diag;
+            atomicAdd(f, v);
+        }
+    }
+}
+
+hipError_t launch_job_stats(const Job* jobs_dev, int32_t njobs, int64_t max_n, const RowStat* row_stats,
+                            JobStats* jstats, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_n + 4095) / 4096, 256));
+    hipLaunchKernelGGL(k_job_stats, dim3(gx, njobs), dim3(256), 0, st, jobs_dev, njobs, row_stats, jstats);
     return hipGetLastError();
 }
 
