@@ -843,12 +843,12 @@ struct Engine {
         // sources in flight for a mapping: the resident wavefronts (or blocks),
         // within half of the memory left after the fixed part
         auto plan_slots = [&](int map) {
-            // large matrices: five of every six resident one-wavefront slots, measured
-            // 2-5 % faster than all six on the 64^3 and 1000^2 stencils (less L2
-            // contention between label arrays of 1-4 MB); small ones (the batch)
-            // were 7 % faster with all six
+            // every resident slot, but at most 16 GiB of label arrays in flight:
+            // the 64^3 stencil (1 MB per source) was fastest with all 6,144 slots,
+            // the 1000^2 stencil (4 MB per source) with 4,096 (321 against 331 ms)
             int64_t want = plan.nslots > 0 ? plan.nslots : (int64_t)traverse_resident_slots(di.cus, map);
-            if (plan.nslots <= 0 && (map == 0 || map == 3) && want >= 1536 && N >= 65536) want = want * 5 / 6;
+            if (plan.nslots <= 0 && (map == 0 || map == 3))
+                want = std::min<int64_t>(want, std::max<int64_t>(1024, (int64_t(16) << 30) / (4 * N)));
             want = std::min<int64_t>(want, std::max<int64_t>(items, 1));
             int64_t ns = std::max<int64_t>(std::min<int64_t>(want, slot_fit), 1);
             // coarse steps, so that small budget changes between calls keep the

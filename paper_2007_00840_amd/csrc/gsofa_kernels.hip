@@ -232,6 +232,7 @@ struct WaveTile {
 constexpr int kTravWaves = 4;
 constexpr int kIlp = 4;          // edges in flight per lane
 constexpr int kHashBits = 9;     // per-wavefront push filter: 512 (level, vertex) entries
+constexpr int kLaneRowMax = 12;  // frontier chunks with rows up to this long: a lane per row
 
 #define GLOBAL __attribute__((address_space(1)))
 template <typename T>
@@ -540,9 +541,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                             nq += __popcll(m);
                         }
                     };
+                    // The chunk's edges, concatenated, are dealt kIlp consecutive ones
+                    // per lane: a lane finds the frontier vertex owning its first edge
+                    // by binary search over the degree prefix in LDS and steps to the
+                    // next vertices for the others. One column-index load instruction
+                    // then covers 64 x kIlp x 4 contiguous bytes instead of one entry of
+                    // 64 different rows, which keeps the address and cache units
+                    // (the measured bottleneck) from processing 64 lines per load.
                     const int32_t maxdeg = wave_max(deg);
-                    if (maxdeg <= 64) {
-                        // short rows: each lane walks its own frontier's row
+                    if (maxdeg <= kLaneRowMax) {
+                        // very short rows: each lane walks its own frontier's row (no
+                        // search; the loads of a round then hit up to 64 rows each)
                         for (int32_t t0 = 0; t0 < maxdeg; t0 += kIlp) {
                             int32_t widx[kIlp];
                             uint32_t outv[kIlp];
@@ -555,32 +564,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                             }
                             round(widx, outv, act_e);
                         }
-                    } else {
-                        // long rows: the chunk's edges are spread evenly over the lanes
-                        T.scan[ln] = incl;
-                        T.start[ln] = fs;
-                        T.outv[ln] = ov;
                         wave_fence();
-                        for (int32_t r0 = 0; r0 < total; r0 += 64 * kIlp) {
-                            int32_t widx[kIlp];
-                            uint32_t outv[kIlp];
-                            bool act_e[kIlp];
-#pragma unroll
-                            for (int kk = 0; kk < kIlp; ++kk) {
-                                const int32_t ei = r0 + kk * 64 + ln;
-                                int32_t jl = 0, jh = 63;
-                                while (jl < jh) {
-                                    const int32_t mid = (jl + jh) >> 1;
-                                    if (T.scan[mid] > ei) jh = mid;
-                                    else jl = mid + 1;
-                                }
-                                const int32_t excl = jl ? T.scan[jl - 1] : 0;
-                                act_e[kk] = ei < total;
-                                widx[kk] = act_e[kk] ? T.start[jl] + (ei - excl) : 0;
-                                outv[kk] = T.outv[jl];
-                            }
-                            round(widx, outv, act_e);
+                        continue;
+                    }
+                    T.scan[ln] = incl;
+                    T.start[ln] = fs;
+                    T.outv[ln] = ov;
+                    wave_fence();
+                    for (int32_t r0 = 0; r0 < total; r0 += 64 * kIlp) {
+                        const int32_t e0 = r0 + ln * kIlp;
+                        int32_t jl = 0, jh = 63;
+                        while (jl < jh) {
+                            const int32_t mid = (jl + jh) >> 1;
+                            if (T.scan[mid] > e0) jh = mid;
+                            else jl = mid + 1;
                         }
+                        int32_t widx[kIlp];
+                        uint32_t outv[kIlp];
+                        bool act_e[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            const int32_t ei = e0 + kk;
+                            act_e[kk] = ei < total;
+                            while (act_e[kk] && jl < 63 && T.scan[jl] <= ei) ++jl;
+                            const int32_t excl = jl ? T.scan[jl - 1] : 0;
+                            widx[kk] = act_e[kk] ? T.start[jl] + (ei - excl) : 0;
+                            outv[kk] = T.outv[jl];
+                        }
+                        round(widx, outv, act_e);
                     }
                     wave_fence();
                 }
