@@ -136,6 +136,39 @@ def bench_batch(g, torch, synth, reps):
             "phases_ms": phases}
 
 
+def bench_ablations(g, torch, synth, m, rp, ci):
+    """The paper's ablations on the headline workload, one call each after a
+    warm-up: the access-order check off (line 9.5), the paper's breadth-first
+    frontier order instead of windows, 32-bit labels vs byte states, and the
+    window span; results are identical, time and revisits differ."""
+    stream = torch.cuda.current_stream().cuda_stream
+    cases = [("windowed, window 16 (default)", dict(window=16, flags=g.MAP_WAVE32)),
+             ("windowed, window 64", dict(window=64, flags=g.MAP_WAVE32)),
+             ("access-order check off (line 9.5)", dict(window=16, flags=g.MAP_WAVE32 | g.NO_LINE95)),
+             ("breadth-first order (paper)", dict(flags=g.MAP_WAVE32 | g.LEVEL_ORDER)),
+             ("byte states, window 16", dict(window=16, flags=g.MAP_BYTE))]
+    out = []
+    ref = None
+    for name, kw in cases:
+        kw = dict(kw)
+        kw["flags"] |= g.RESULT_ON_DEVICE | g.NO_TUNE
+        r = g.symbolic(m.n, rp, ci, stream=stream, **kw)  # warm-up (slot sets, pool size)
+        r.free()
+        r = g.symbolic(m.n, rp, ci, stream=stream, **kw)
+        st = r.stats
+        fills = r.fills
+        r.free()
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = fills
+        row = {"case": name, "t_traverse_ms": round(st["t_traverse_ms"], 3), "edges_alg": st["edges_alg"],
+               "edges_gpu": st["edges_gpu"], "revisit_ratio": round(st["edges_gpu"] / max(st["edges_alg"], 1), 4),
+               "levels": st["iterations"], "windows": st["windows"], "same_fills": fills == ref}
+        log(f"ablation: {row}")
+        out.append(row)
+    return out
+
+
 def bench_2d(g, torch, synth, steps):
     """The 2D workload (9-point stencil on a 1000 x 1000 grid, nested
     dissection, drop 0.2): one warm-up call (tunes its size class), then
@@ -286,6 +319,8 @@ def main():
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--twod-steps", type=int, default=2, help="timed calls on the 2D workload (0 = skip)")
+    ap.add_argument("--ablations", action="store_true",
+                    help="also time the paper's ablations on the headline workload")
     ap.add_argument("--batch-reps", type=int, default=3, help="0 = skip the batch measurement")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="wall cap of the request-stream measurement (0 = skip)")
@@ -353,6 +388,7 @@ def main():
     log(f"steps: {ms:.1f} ms/step, traverse {t_trav:.1f} ms, emit {t_emit:.1f} ms, "
         f"supernode {t_sn:.1f} ms, {gteps:.1f} GTEPS")
 
+    ablations = bench_ablations(g, torch, synth, m, rp, ci) if args.ablations else None
     twod = bench_2d(g, torch, synth, args.twod_steps) if args.twod_steps > 0 else None
     g.release_cache()  # the 2D workload's slot sets are not reused below
     batch = bench_batch(g, torch, synth, args.batch_reps) if args.batch_reps > 0 else None
@@ -399,6 +435,7 @@ def main():
         "concurrent_sources": stats[-1]["concurrent_sources"],
         "window": stats[-1]["window"], "mapping": stats[-1]["mapping"],
         "t_tune_ms_warmup": round(max(s["t_tune_ms"] for s in warm_stats), 3) if warm_stats else 0.0,
+        "ablations": ablations,
         "workload_2d": twod,
         "batch": batch,
         "serve": serve,
