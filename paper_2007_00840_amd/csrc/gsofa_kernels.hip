@@ -549,7 +549,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                     // 64 different rows, which keeps the address and cache units
                     // (the measured bottleneck) from processing 64 lines per load.
                     const int32_t maxdeg = wave_max(deg);
-                    if (maxdeg <= kLaneRowMax) {
+                    // a lane per row for short rows, unless dealing the edges takes
+                    // fewer rounds (a small frontier: one round instead of maxdeg / 4)
+                    if (maxdeg <= kLaneRowMax && !(total <= 64 * kIlp && maxdeg > kIlp)) {
                         // very short rows: each lane walks its own frontier's row (no
                         // search; the loads of a round then hit up to 64 rows each)
                         for (int32_t t0 = 0; t0 < maxdeg; t0 += kIlp) {
