@@ -319,8 +319,8 @@ def main():
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--twod-steps", type=int, default=2, help="timed calls on the 2D workload (0 = skip)")
-    ap.add_argument("--ablations", action="store_true",
-                    help="also time the paper's ablations on the headline workload")
+    ap.add_argument("--skip-ablations", action="store_true",
+                    help="do not time the paper's ablations on the headline workload")
     ap.add_argument("--batch-reps", type=int, default=3, help="0 = skip the batch measurement")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="wall cap of the request-stream measurement (0 = skip)")
@@ -388,7 +388,7 @@ def main():
     log(f"steps: {ms:.1f} ms/step, traverse {t_trav:.1f} ms, emit {t_emit:.1f} ms, "
         f"supernode {t_sn:.1f} ms, {gteps:.1f} GTEPS")
 
-    ablations = bench_ablations(g, torch, synth, m, rp, ci) if args.ablations else None
+    ablations = None if args.skip_ablations else bench_ablations(g, torch, synth, m, rp, ci)
     twod = bench_2d(g, torch, synth, args.twod_steps) if args.twod_steps > 0 else None
     g.release_cache()  # the 2D workload's slot sets are not reused below
     batch = bench_batch(g, torch, synth, args.batch_reps) if args.batch_reps > 0 else None

@@ -760,9 +760,13 @@ struct Engine {
             chk(hipStreamSynchronize(st));
             for (int32_t j = 0; j < nj; ++j) {
                 const int64_t last = h_last.as<int64_t>()[j];
-                if (last < 0) jstat[j] = GSOFA_EINVAL;
+                // a negative count, or entries with no column array, is malformed
+                if (last < 0 || (last > 0 && !mats[j].ci)) jstat[j] = GSOFA_EINVAL;
                 nnz[j] = std::max<int64_t>(last, 0);
             }
+            // nothing may read such a matrix's arrays: fail before the validation kernel
+            for (int32_t j = 0; j < nj; ++j)
+                if (jstat[j] != GSOFA_OK) return finish_failed(jstat, t0);
         } else {
             std::vector<int64_t> rp_off(nj), ci_off(nj);
             int64_t rp_tot = 0, ci_tot = 0;

@@ -1,5 +1,6 @@
 """GPU parity: the HIP path (called through the C ABI) against the CPU oracle,
 element by element on the same seeded inputs. Integer results: bit-exact."""
+import ctypes
 import sys
 
 import numpy as np
@@ -228,6 +229,14 @@ def test_device_input_errors(g):
     with pytest.raises(g.GsofaError) as e:
         g.symbolic(m.n, torch.from_numpy(m.row_ptr).cuda(), torch.from_numpy(ci).cuda())
     assert e.value.code == g.EINVAL
+    # entries but no column array: rejected before any kernel reads it
+    lib = g.load()
+    out = ctypes.POINTER(g.Result)()
+    o = g.Opts()
+    o.flags = g.INPUT_ON_DEVICE
+    rp_d = torch.from_numpy(m.row_ptr).cuda()
+    assert lib.gsofa_symbolic(m.n, ctypes.c_void_p(rp_d.data_ptr()), None, ctypes.byref(o),
+                              ctypes.byref(out)) == g.EINVAL
     # the library stays usable afterwards
     ref = run_ref(m.n, m.row_ptr, m.col_idx)
     assert_same(g.symbolic(m.n, m.row_ptr, m.col_idx), ref)
