@@ -198,9 +198,13 @@ GSOFA_API int gsofa_batch(int32_t count, const gsofa_csr* mats, const gsofa_opts
 /*
  * Request server with continuous batching: requests are admitted in arrival
  * order while their estimated device memory fits the budget
- * (opts->mem_budget_bytes) and fewer than max_inflight are running; admitted
- * requests run concurrently on the device and finished ones release their
- * memory, which admits the next.
+ * (opts->mem_budget_bytes, default: free device memory plus what the library
+ * holds idle) and fewer than max_inflight workers are busy; a worker that
+ * admits a request of at most 65,536 rows also takes the later queued small
+ * requests that fit (up to 64 and 2^20 rows together) and runs them as one
+ * persistent launch, as gsofa_batch does. Admitted work runs concurrently on
+ * the device and finished requests release their memory, which admits the
+ * next. Requests never time tuner trials (cached choices or defaults).
  *   serve_submit copies the CSR (host pointers) and returns a ticket.
  *     GSOFA_ECAPACITY if the request alone can never fit the budget.
  *   serve_poll waits up to timeout_us microseconds (0 = just test,

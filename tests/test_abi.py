@@ -125,3 +125,27 @@ def test_graph_counters_argument_error(g):
     assert lib.gsofa_graph_counters(None) == g.EINVAL
     a = g.graph_counters()
     assert len(a) == 3 and all(x >= 0 for x in a)
+
+
+def test_bench_reads_its_traffic_record():
+    """bench.py takes roofline.traffic from the committed PMC record only for
+    the configuration the record names."""
+    import os
+    import sys
+    here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, here)
+    import bench
+    import re
+    text = open(os.path.join(here, "profiles", "k_traverse_64cube_27pt.md")).read()
+    m = re.search(r"traffic-record: kernel=(\S+) source_sha256_16=(\S+) mapping=(\d+) window=(\d+) "
+                  r"sources=(\d+) fetch_bytes=(\d+) write_bytes=(\d+)", text)
+    assert m, "profile summary lacks its traffic record"
+    kernel, mapping, window, sources = m.group(1), int(m.group(3)), int(m.group(4)), int(m.group(5))
+    want = int(m.group(6)) + int(m.group(7))
+    got = bench.recorded_traffic(kernel, mapping, window, sources)
+    if m.group(2) == bench.traversal_source_hash():
+        assert got == want
+    else:
+        assert got is None  # the kernel changed since the counters were taken
+    assert bench.recorded_traffic(kernel, mapping, window + 1, sources) is None
+    assert bench.recorded_traffic(kernel, mapping, window, sources + 4) is None
