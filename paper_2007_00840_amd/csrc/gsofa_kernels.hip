@@ -459,7 +459,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                     e_gpu += (unsigned long long)total;
                     // one round: kIlp independent edges per lane; every load of the
                     // round is issued before any of its results is used
-                    auto round = [&](int32_t (&widx)[kIlp], uint32_t (&outv)[kIlp], bool (&act_e)[kIlp]) {
+                    // own[k]: lane holding the row of edge k. A lane's row passes on
+                    // ov, or with refresh set the value decoded from fraw (its label
+                    // re-read); both are taken once the round's loads are in flight.
+                    auto round = [&](int32_t (&widx)[kIlp], int32_t (&own)[kIlp], uint32_t fraw, bool refresh,
+                                     bool (&act_e)[kIlp]) {
                         int32_t w[kIlp];
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) w[kk] = ci[widx[kk]];
@@ -470,6 +474,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                             const uint32_t off = act_e[kk] ? (uint32_t)w[kk] * 4u : 0xFFFFFFF0u;
                             lv[kk] = __builtin_amdgcn_raw_buffer_load_b32(lab_r, off, 0, 0);
                         }
+                        const uint32_t dr = dec(fraw);
+                        const uint32_t ovr = refresh ? ((dr == kInf) ? kInf : max(dr, (uint32_t)f)) : ov;
+                        uint32_t outv[kIlp];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) outv[kk] = (uint32_t)__shfl((int)ovr, own[kk], 64);
                         // which edges can change a label: U side unseen, or a smaller value
                         bool cand[kIlp];
 #pragma unroll
@@ -574,11 +583,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                     }
                     const int32_t nr = (total + 64 * kIlp - 1) / (64 * kIlp);
                     for (int32_t rr = 0; rr < nr; ++rr) {
-                        uint32_t ovr = ov;
-                        if (rr > 0 && has) {
-                            const uint32_t d = dec(ld_coherent(&lab[f]));
-                            ovr = (d == kInf) ? kInf : max(d, (uint32_t)f);
-                        }
+                        // issued first, used only once the round's loads are in flight;
+                        // sc0 (aux 1) as for a coherent load, an out-of-range offset
+                        // (no refresh) returns 0 without a memory access
+                        const bool refresh = rr > 0 && has;
+                        const uint32_t fraw = __builtin_amdgcn_raw_buffer_load_b32(
+                            lab_r, refresh ? (uint32_t)f * 4u : 0xFFFFFFF0u, 0, 1);
                         const int32_t r0 = rr * (64 * kIlp);
                         const int32_t W0 = r0 & ~(kHeadEdges - 1);
                         if (r0 == W0) {
@@ -591,8 +601,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
                             wave_fence();
                         }
-                        int32_t widx[kIlp];
-                        uint32_t outv[kIlp];
+                        int32_t widx[kIlp], own[kIlp];
                         bool act_e[kIlp];
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
@@ -604,9 +613,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                                               __popcll(hd & ((2ull << ln) - 1ull) & ~1ull);
                             const int2 q = T.pk[o];
                             widx[kk] = act_e[kk] ? q.x + ei : 0;
-                            outv[kk] = (uint32_t)__shfl((int)ovr, q.y, 64);
+                            own[kk] = q.y;
                         }
-                        round(widx, outv, act_e);
+                        round(widx, own, fraw, refresh, act_e);
                     }
                     wave_fence();
                 }
