@@ -244,6 +244,11 @@ struct DealTile {
 constexpr int kTravWaves = 4;
 constexpr int kIlp = 4;          // edges in flight per lane
 constexpr int kHashBits = 9;     // per-wavefront push filter: 512 (level, vertex) entries
+// per-wavefront table that keeps one atomic minimum per target vertex and round
+// (128 entries; a key holds the vertex id's bits above these 7, a 31-bit value and
+// an 8-bit edge slot), used by rounds with at least kDedupMin candidate edges
+constexpr int kDedupBits = 7;
+constexpr int kDedupMin = 32;
 
 #define GLOBAL __attribute__((address_space(1)))
 template <typename T>
@@ -268,12 +273,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t label_rsrc(uint32_t* lab, int6
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_traverse(TraverseArgs a) {
     __shared__ DealTile tiles[kTravWaves];
     __shared__ unsigned long long pushed[kTravWaves][1 << kHashBits];
+    __shared__ unsigned long long rdedup[kTravWaves][1 << kDedupBits];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ln = lane_id();
     const int32_t slot = blockIdx.x * kTravWaves + wv;
     if (slot >= a.nslots) return;
     DealTile& T = tiles[wv];
     unsigned long long* H = pushed[wv];
+    unsigned long long* RT = rdedup[wv];
 
     uint8_t* sb = a.slots + (int64_t)slot * a.lay.bytes_per_slot;
     GLOBAL uint32_t* lab = gbl((uint32_t*)(sb + a.lay.off_lab));
@@ -342,7 +349,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
             return (v >= base && v - base < R) ? v - base : kInf;
         };
 
-        unsigned long long e_alg = 0, e_gpu = 0;
+        // a source's first-visit degrees sum to at most nnz < 2^31: 32 bits per lane
+        uint32_t e_alg = 0;
+        unsigned long long e_gpu = 0;
         int32_t rcount = 0, lcount = 0;
         uint32_t n_iter = 0, n_win = 0;
 
@@ -371,11 +380,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
             lcount += __popcll(__ballot(below));
             if (below) {
                 wg_or(&P[w >> 6], 1ull << (w & 63));
-                e_alg += (unsigned long long)(rp[w + 1] - rp[w]);
+                e_alg += (uint32_t)(rp[w + 1] - rp[w]);
                 pmin = min(pmin, w);
             }
         }
-        if (ln == 0) e_alg += (unsigned long long)(re - rs);
+        if (ln == 0) e_alg += (uint32_t)(re - rs);
         e_gpu += (unsigned long long)(re - rs);
         if (__ballot(dup) != 0ull || ndiag > 1) {
             if (ln == 0) atomicOr(&a.jstats[j].err, kErrDuplicate);
@@ -451,7 +460,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                     const int32_t f = fr & 0x7FFFFFFF;
                     const int32_t fs = rp[f];
                     const int32_t deg = act ? rp[f + 1] - fs : 0;
-                    if (fr < 0) e_alg += (unsigned long long)deg;
+                    if (fr < 0) e_alg += (uint32_t)deg;
                     const uint32_t dl = dec(ld_coherent(&lab[f]));
                     const uint32_t ov = (dl == kInf) ? kInf : max(dl, (uint32_t)f);
                     const int32_t incl = wave_incl_scan(deg);
@@ -486,6 +495,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                             const uint32_t d = dec(lv[kk]);
                             if (w[kk] > s) cand[kk] = act_e[kk] && d == kInf;
                             else cand[kk] = act_e[kk] && outv[kk] < d && !(line95 && d < (uint32_t)w[kk]);
+                        }
+                        // Candidates of one round that share a target all saw the label
+                        // as it was before the round; only the one with the smallest value
+                        // (ties: the lowest edge slot) needs its atomic minimum: the others
+                        // could not lower the label below it, and the one issued returns
+                        // the label every decision below needs. Without this, about half
+                        // the atomics of a 2D 9-point or 3D 27-point traversal changed
+                        // nothing (neighbouring rows of a round share most neighbours).
+                        // They meet in a small LDS table: slot from a fold of w, key =
+                        // (w's high bits, value, edge slot), so equal keys mean the same
+                        // edge and a slot holding another vertex leaves the candidate as
+                        // it is. Rounds with few candidates skip it (the LDS round trips
+                        // then cost more than the atomics they save).
+                        const int32_t ncand = __popcll(__ballot(cand[0])) + __popcll(__ballot(cand[1])) +
+                                              __popcll(__ballot(cand[2])) + __popcll(__ballot(cand[3]));
+                        if (ncand >= kDedupMin) {
+                            // slot and key are recomputed in each phase (cheaper than
+                            // keeping them in registers across the LDS round trips)
+                            auto slot = [&](int kk) -> uint32_t {
+                                uint32_t wv = (uint32_t)w[kk];
+                                asm volatile("" : "+v"(wv));
+                                return (wv ^ (wv >> kDedupBits) ^ (wv >> (2 * kDedupBits))) & ((1u << kDedupBits) - 1u);
+                            };
+                            auto keyof = [&](int kk) -> unsigned long long {
+                                uint32_t wv = (uint32_t)w[kk];
+                                asm volatile("" : "+v"(wv));
+                                return ((unsigned long long)(wv >> kDedupBits) << 39) |
+                                       ((unsigned long long)(wv > (uint32_t)s ? 0u : outv[kk]) << 8) |
+                                       (unsigned long long)(kk * 64 + ln);
+                            };
+#pragma unroll
+                            for (int kk = 0; kk < kIlp; ++kk)
+                                if (cand[kk]) RT[slot(kk)] = ~0ull;
+                            wave_fence();
+#pragma unroll
+                            for (int kk = 0; kk < kIlp; ++kk)
+                                if (cand[kk])
+                                    __hip_atomic_fetch_min(&RT[slot(kk)], keyof(kk), __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+                            wave_fence();
+#pragma unroll
+                            for (int kk = 0; kk < kIlp; ++kk) {
+                                if (cand[kk]) {
+                                    const unsigned long long r = RT[slot(kk)], kq = keyof(kk);
+                                    cand[kk] = r == kq || (r >> 39) != (kq >> 39);
+                                }
+                            }
                         }
                         uint32_t old[kIlp];
 #pragma unroll
@@ -542,7 +598,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                         bool any = false;
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
-                            if (first[kk] && !push[kk]) e_alg += (unsigned long long)(rp[w[kk] + 1] - rp[w[kk]]);
+                            if (first[kk] && !push[kk]) e_alg += (uint32_t)(rp[w[kk] + 1] - rp[w[kk]]);
                             any |= emit[kk] | push[kk];
                         }
                         if (__ballot(any) == 0ull) return;
@@ -646,9 +702,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
             if (!fits) atomicOr(&a.jstats[j].err, kErrOverflow);
         }
 
-        e_alg = wave_sum_u64(e_alg);
+        const unsigned long long e_alg_s = wave_sum_u64((unsigned long long)e_alg);
         if (ln == 0 && a.row_stats)
-            a.row_stats[grow] = RowStat{e_alg, e_gpu, n_iter, (n_win & 0x7FFFFFFFu) | (ndiag > 0 ? 0x80000000u : 0u)};
+            a.row_stats[grow] = RowStat{e_alg_s, e_gpu, n_iter, (n_win & 0x7FFFFFFFu) | (ndiag > 0 ? 0x80000000u : 0u)};
         slot_fence();
     }
     if (ln == 0) {
