@@ -151,6 +151,33 @@ def test_generator_families(g, idx):
     assert_same(g.symbolic(m.n, m.row_ptr, m.col_idx), ref)
 
 
+def _shared_targets(k, width, n, seed):
+    """Rows 0..k-1 all have entries in the same `width` columns k..k+width-1, and
+    later rows (sources above and inside that column range) reach rows 0..k-1: one
+    traversal round then holds several edges to each not yet reached target, on
+    the L side and on the U side of the source (the in-round atomic filter keeps
+    one per target)."""
+    rng = np.random.default_rng(seed)
+    D = np.eye(n, dtype=bool)
+    D[:k, k:k + width] = True
+    D[k + width:k + width + 12, :k] = True      # sources above the shared columns
+    D[k:k + 6, :k] = True                       # sources inside them (U-side targets)
+    D |= rng.random((n, n)) < 1.5 / n
+    return _csr_from_dense(D)
+
+
+@pytest.mark.parametrize("case", [(16, 64, 300, 1, 0), (16, 200, 300, 2, 0), (40, 32, 300, 3, 0),
+                                  (8, 250, 300, 4, 0), (60, 150, 300, 5, 64), (16, 64, 300, 6, 1),
+                                  (64, 200, 400, 7, 253)], ids=str)
+def test_shared_targets_in_one_round(g, case):
+    k, width, n, seed, window = case
+    rp, ci = _shared_targets(k, width, n, seed)
+    _say(f"shared targets k={k} width={width} n={n} window={window}")
+    ref = run_ref(n, rp, ci)
+    assert_same(g.symbolic(n, rp, ci, window=window), ref)
+    assert_same(g.symbolic(n, rp, ci, window=window, flags=0x800), ref)
+
+
 @pytest.mark.parametrize("kw", [
     {"window": 1}, {"window": 3}, {"window": 64}, {"window": 5000},
     {"flags": 0x20}, {"flags": 0x10}, {"concurrent_sources": 1}, {"concurrent_sources": 7},
