@@ -639,13 +639,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                     }
                     const int32_t nr = (total + 64 * kIlp - 1) / (64 * kIlp);
                     for (int32_t rr = 0; rr < nr; ++rr) {
-                        // issued first, used only once the round's loads are in flight;
-                        // sc0 (aux 1) as for a coherent load, an out-of-range offset
-                        // (no refresh) returns 0 without a memory access
-                        const bool refresh = rr > 0 && has;
+                        const int32_t r0 = rr * (64 * kIlp);
+                        // only rows with edges in this round re-read their label:
+                        // finished rows pass nothing on, later rows re-read theirs when
+                        // their round comes. Issued first, used only once the round's
+                        // loads are in flight; sc0 (aux 1) as for a coherent load, an
+                        // out-of-range offset (no refresh) returns 0 without an access.
+                        const bool refresh = rr > 0 && has && incl > r0 && excl < r0 + 64 * kIlp;
                         const uint32_t fraw = __builtin_amdgcn_raw_buffer_load_b32(
                             lab_r, refresh ? (uint32_t)f * 4u : 0xFFFFFFF0u, 0, 1);
-                        const int32_t r0 = rr * (64 * kIlp);
                         const int32_t W0 = r0 & ~(kHeadEdges - 1);
                         if (r0 == W0) {
                             // row starts among edges [W0, W0 + kHeadEdges)
