@@ -476,18 +476,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                         int32_t w[kIlp];
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) w[kk] = ci[widx[kk]];
+#pragma unroll
+                        for (int kk = 0; kk < kIlp; ++kk) act_e[kk] = act_e[kk] && w[kk] != s;
+                        // slot and key of edge kk in the per-round dedup table (below),
+                        // recomputed where used: cheaper than keeping them in registers
+                        // across the LDS round trips
+                        auto slot = [&](int kk) -> uint32_t {
+                            uint32_t wv = (uint32_t)w[kk];
+                            asm volatile("" : "+v"(wv));
+                            return (wv ^ (wv >> kDedupBits) ^ (wv >> (2 * kDedupBits))) & ((1u << kDedupBits) - 1u);
+                        };
+                        uint32_t outv[kIlp];
                         uint32_t lv[kIlp];
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
-                            act_e[kk] = act_e[kk] && w[kk] != s;
                             const uint32_t off = act_e[kk] ? (uint32_t)w[kk] * 4u : 0xFFFFFFF0u;
                             lv[kk] = __builtin_amdgcn_raw_buffer_load_b32(lab_r, off, 0, 0);
                         }
-                        const uint32_t dr = dec(fraw);
-                        const uint32_t ovr = refresh ? ((dr == kInf) ? kInf : max(dr, (uint32_t)f)) : ov;
-                        uint32_t outv[kIlp];
+                        {
+                            const uint32_t dr = dec(fraw);
+                            const uint32_t ovr = refresh ? ((dr == kInf) ? kInf : max(dr, (uint32_t)f)) : ov;
 #pragma unroll
-                        for (int kk = 0; kk < kIlp; ++kk) outv[kk] = (uint32_t)__shfl((int)ovr, own[kk], 64);
+                            for (int kk = 0; kk < kIlp; ++kk) outv[kk] = (uint32_t)__shfl((int)ovr, own[kk], 64);
+                        }
+                        auto keyof = [&](int kk) -> unsigned long long {
+                            uint32_t wv = (uint32_t)w[kk];
+                            asm volatile("" : "+v"(wv));
+                            return ((unsigned long long)(wv >> kDedupBits) << 39) |
+                                   ((unsigned long long)(wv > (uint32_t)s ? 0u : outv[kk]) << 8) |
+                                   (unsigned long long)(kk * 64 + ln);
+                        };
                         // which edges can change a label: U side unseen, or a smaller value
                         bool cand[kIlp];
 #pragma unroll
@@ -511,20 +529,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                         const int32_t ncand = __popcll(__ballot(cand[0])) + __popcll(__ballot(cand[1])) +
                                               __popcll(__ballot(cand[2])) + __popcll(__ballot(cand[3]));
                         if (ncand >= kDedupMin) {
-                            // slot and key are recomputed in each phase (cheaper than
-                            // keeping them in registers across the LDS round trips)
-                            auto slot = [&](int kk) -> uint32_t {
-                                uint32_t wv = (uint32_t)w[kk];
-                                asm volatile("" : "+v"(wv));
-                                return (wv ^ (wv >> kDedupBits) ^ (wv >> (2 * kDedupBits))) & ((1u << kDedupBits) - 1u);
-                            };
-                            auto keyof = [&](int kk) -> unsigned long long {
-                                uint32_t wv = (uint32_t)w[kk];
-                                asm volatile("" : "+v"(wv));
-                                return ((unsigned long long)(wv >> kDedupBits) << 39) |
-                                       ((unsigned long long)(wv > (uint32_t)s ? 0u : outv[kk]) << 8) |
-                                       (unsigned long long)(kk * 64 + ln);
-                            };
 #pragma unroll
                             for (int kk = 0; kk < kIlp; ++kk)
                                 if (cand[kk]) RT[slot(kk)] = ~0ull;
