@@ -178,6 +178,28 @@ def test_shared_targets_in_one_round(g, case):
     assert_same(g.symbolic(n, rp, ci, window=window, flags=0x800), ref)
 
 
+def test_full_rows_span_several_sort_chunks(g):
+    """Row 0 and the last three rows hold every column and each other row a band
+    entry: the U row of 0 and the L rows of the last three span more ids than one
+    LDS bitmap chunk of the row sort, so they are ranked over several chunks."""
+    n = 300_000
+    rows = []
+    full = np.arange(n, dtype=np.int32)
+    for i in range(n):
+        if i == 0 or i >= n - 3:
+            rows.append(full)
+        elif i + 7 < n:
+            rows.append(np.array([i, i + 7], dtype=np.int32))
+        else:
+            rows.append(np.array([i], dtype=np.int32))
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.concatenate(rows).astype(np.int32)
+    _say(f"full rows n={n} nnz={len(ci)}")
+    ref = run_ref(n, rp, ci)
+    assert_same(g.symbolic(n, rp, ci), ref)
+
+
 @pytest.mark.parametrize("kw", [
     {"window": 1}, {"window": 3}, {"window": 64}, {"window": 5000},
     {"flags": 0x20}, {"flags": 0x10}, {"concurrent_sources": 1}, {"concurrent_sources": 7},
