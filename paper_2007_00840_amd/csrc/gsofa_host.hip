@@ -626,8 +626,9 @@ int32_t auto_window(int64_t sources) {
 // Window span and traversal mapping change only the speed, never the result.
 // For a size class that has not been seen yet (device, log2 of the largest n,
 // mean row length, batch size) and a call with enough sources, the tuner times
-// every candidate on the same stratified sample of the call's sources (8 per
-// slot), keeps the fastest, and reuses it for later calls of the class.
+// every candidate on the same stratified sample of the call's sources
+// (kTuneSamplesPerSlot per slot), keeps the fastest, and reuses it for later
+// calls of the class.
 // Smaller calls use the defaults. The number of sources in flight is not tuned:
 // on a sample a few sources per slot long, fewer slots win by balancing the
 // tail better, while at full size they were twice as slow, so every candidate
