@@ -268,10 +268,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t label_rsrc(uint32_t* lab, int6
 // For w > s the first atomic minimum that finds a stale word marks the U entry.
 // The label is read first and the atomic minimum is issued only where it can
 // lower it (an atomic on every edge instead measured 4x slower).
-// Seven wavefronts per SIMD (at most 72 VGPRs; what spills is per-source set-up,
+// Eight wavefronts per SIMD (at most 64 VGPRs; what spills is per-source set-up,
 // outside the level loop; the LDS tables take 15 KB per workgroup of four): more
-// loads in flight than six (80 VGPRs, 3 % slower on the 64^3 27-point stencil).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_traverse(TraverseArgs a) {
+// loads in flight than seven (72 VGPRs) or six (80), which were 4 % and 7 % slower
+// on the 64^3 27-point stencil.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_traverse(TraverseArgs a) {
     __shared__ DealTile tiles[kTravWaves];
     __shared__ unsigned long long pushed[kTravWaves][1 << kHashBits];
     __shared__ unsigned long long rdedup[kTravWaves][1 << kDedupBits];
