@@ -1356,7 +1356,12 @@ struct Engine {
         TuneChoice best = kTuneCandidates[0];
         float best_ms = 0;
         bool have = false;
-        for (const TuneChoice& c : kTuneCandidates) {
+        // The first candidate runs once untimed: the first launch on a new slot
+        // set also pays for touching its memory, which made that candidate lose
+        // by ~7 % to an equal one on the 64^3 27-point stencil.
+        constexpr int kCand = (int)(sizeof(kTuneCandidates) / sizeof(kTuneCandidates[0]));
+        for (int t = -1; t < kCand; ++t) {
+            const TuneChoice& c = kTuneCandidates[t < 0 ? 0 : t];
             const int64_t ns = plan_slots(c.mapping);
             auto ss = take_slots(lay, (int32_t)ns, c.mapping == 3 ? 1 : 0, st);
             TraverseArgs ta{};
@@ -1388,6 +1393,7 @@ struct Engine {
             chk(hipEventRecord(ev[1], st));
             chk(hipStreamSynchronize(st));
             give_slots(std::move(ss));
+            if (t < 0) continue;
             float ms = 0;
             chk(hipEventElapsedTime(&ms, ev[0], ev[1]));
             if (!have || ms < best_ms * 0.95f) {
