@@ -55,13 +55,15 @@ def recorded_traffic(kernel, mapping, window, sources):
         text = open(rec).read()
     except OSError:
         return None
-    m = re.search(r"traffic-record: kernel=(\S+) source_sha256_16=(\S+) mapping=(\d+) window=(\d+) "
-                  r"sources=(\d+) fetch_bytes=(\d+) write_bytes=(\d+)", text)
-    if not m or m.group(1) != kernel or m.group(2) != sha:
-        return None
-    if int(m.group(3)) != mapping or int(m.group(4)) != window or int(m.group(5)) != sources:
-        return None
-    return int(m.group(6)) + int(m.group(7))
+    # one record per configuration the tuner may pick (its near-tie windows)
+    for m in re.finditer(r"traffic-record: kernel=(\S+) source_sha256_16=(\S+) mapping=(\d+) window=(\d+) "
+                         r"sources=(\d+) fetch_bytes=(\d+) write_bytes=(\d+)", text):
+        if m.group(1) != kernel or m.group(2) != sha:
+            continue
+        if int(m.group(3)) != mapping or int(m.group(4)) != window or int(m.group(5)) != sources:
+            continue
+        return int(m.group(6)) + int(m.group(7))
+    return None
 
 
 def cpu_baseline(m, stride):
