@@ -849,8 +849,9 @@ struct Engine {
         // within half of the memory left after the fixed part
         auto plan_slots = [&](int map) {
             // every resident slot, but at most 16 GiB of label arrays in flight:
-            // the 64^3 stencil (1 MB per source) was fastest with all 6,144 slots,
-            // the 1000^2 stencil (4 MB per source) with 4,096 (321 against 331 ms)
+            // the 64^3 stencil (1 MB per source) is fastest with all resident
+            // slots (8,192), the 1000^2 stencil (4 MB per source) gained nothing
+            // beyond 4,096
             int64_t want = plan.nslots > 0 ? plan.nslots : (int64_t)traverse_resident_slots(di.cus, map);
             if (plan.nslots <= 0 && (map == 0 || map == 3))
                 want = std::min<int64_t>(want, std::max<int64_t>(1024, (int64_t(16) << 30) / (4 * N)));
