@@ -312,7 +312,8 @@ def bench_serve(g, synth, cap_s, low_rate):
 
 
 # traversal kernel launched for each mapping code reported in the stats
-KERNEL_OF_MAPPING = {3: "k_traverse8", 0: "k_traverse", 2: "k_traverse_wg<8>", 1: "k_traverse_wg<16>"}
+KERNEL_OF_MAPPING = {3: "k_traverse8", 0: "k_traverse", 4: "k_traverse<7>", 2: "k_traverse_wg<8>",
+                     1: "k_traverse_wg<16>"}
 
 
 def main():

@@ -81,6 +81,10 @@ typedef enum {
 #define GSOFA_MAP_WG16          0x100u /* sixteen wavefronts per source row            */
 #define GSOFA_MAP_BYTE          0x800u /* one wavefront per source row, one state byte
                                           per vertex (windows up to 253 ids)          */
+#define GSOFA_MAP_WAVE32_7      0x1000u /* as GSOFA_MAP_WAVE32, the kernel compiled for
+                                          seven instead of eight wavefronts per SIMD
+                                          (fewer sources in flight, less spilled per
+                                          source)                                      */
 /* By default the device work of a call between two host synchronisations
  * (traversal; pointer scans; row sort; supernodes; L transpose and result
  * pointers) is captured into HIP graphs and each phase is one graph launch;
@@ -125,8 +129,9 @@ typedef struct {
     double t_total_ms;          /* whole call, host copies included                       */
     int32_t window;             /* threshold-window span used                             */
     int32_t mapping;            /* traversal mapping used: 0 one wavefront per source with
-                                   32-bit labels, 3 one wavefront with byte states, 2 / 1
-                                   eight / sixteen wavefronts per source                  */
+                                   32-bit labels, 4 the same compiled for seven wavefronts
+                                   per SIMD, 3 one wavefront with byte states, 2 / 1 eight
+                                   / sixteen wavefronts per source                        */
     double t_tune_ms;           /* autotuner trial time spent in this call (0 if none)    */
 } gsofa_stats;
 

@@ -30,6 +30,7 @@ MAP_WG8 = 0x80
 MAP_WG16 = 0x100
 EAGER = 0x200
 MAP_BYTE = 0x800
+MAP_WAVE32_7 = 0x1000
 TUNE_NOW = 0x400
 NO_TUNE = 0x2000
 

@@ -606,6 +606,7 @@ int choose_mapping(uint32_t flags, int32_t window) {
     if (flags & GSOFA_MAP_WG16) return 1;
     if (flags & GSOFA_MAP_WG8) return 2;
     if (flags & GSOFA_MAP_WAVE32) return 0;
+    if (flags & GSOFA_MAP_WAVE32_7) return 4;
     const bool ablation = window > 253 || (flags & (GSOFA_NO_LINE95 | GSOFA_LEVEL_ORDER));
     if ((flags & GSOFA_MAP_BYTE) && !ablation) return 3;
     return 0;
@@ -642,12 +643,16 @@ struct TuneKey {
 };
 
 struct TuneChoice {
-    int mapping;     // 0 32-bit labels, 3 byte states
+    int mapping;     // 0 32-bit labels (eight wavefronts per SIMD), 4 the same at seven, 3 byte states
     int32_t window;  // threshold-window span
 };
 
 constexpr TuneChoice kTuneCandidates[] = {
-    {0, 16}, {0, 32}, {0, 64}, {0, 8}, {3, 16},
+    // order is a prior: a later candidate replaces the best only if 5 % faster.
+    // Seven wavefronts per SIMD with window 8 comes second: where window 8 wins
+    // clearly (the 1000^2 9-point stencil) it also wins at seven by ~4 %, which
+    // the margin would hide if it came after window 8 at eight.
+    {0, 16}, {4, 8}, {0, 32}, {0, 64}, {0, 8}, {4, 16}, {3, 16},
 };
 constexpr int kTuneSamplesPerSlot = 24;
 
@@ -853,14 +858,14 @@ struct Engine {
             // slots (8,192), the 1000^2 stencil (4 MB per source) gained nothing
             // beyond 4,096
             int64_t want = plan.nslots > 0 ? plan.nslots : (int64_t)traverse_resident_slots(di.cus, map);
-            if (plan.nslots <= 0 && (map == 0 || map == 3))
+            if (plan.nslots <= 0 && (map == 0 || map == 3 || map == 4))
                 want = std::min<int64_t>(want, std::max<int64_t>(1024, (int64_t(16) << 30) / (4 * N)));
             want = std::min<int64_t>(want, std::max<int64_t>(items, 1));
             int64_t ns = std::max<int64_t>(std::min<int64_t>(want, slot_fit), 1);
             // coarse steps, so that small budget changes between calls keep the
             // cached slot set; the one-wavefront mappings launch whole blocks of 4
             if (plan.nslots <= 0 && ns > 1024) ns = ns / 256 * 256;
-            if ((map == 0 || map == 3) && ns > 4) ns = ns / 4 * 4;
+            if ((map == 0 || map == 3 || map == 4) && ns > 4) ns = ns / 4 * 4;
             return ns;
         };
         int mapping = choose_mapping(plan.flags, plan.window);
@@ -1474,7 +1479,7 @@ int run_engine(std::vector<MatIn> mats, const gsofa_opts* o, std::vector<gsofa_r
         rows += std::max<int32_t>(m.n, 0);
     }
     eng.plan.window_auto = eng.plan.window <= 0 && eng.plan.nslots <= 0 &&
-                           (eng.plan.flags & (GSOFA_MAP_WAVE32 | GSOFA_MAP_WG8 | GSOFA_MAP_WG16 | GSOFA_MAP_BYTE |
+                           (eng.plan.flags & (GSOFA_MAP_WAVE32 | GSOFA_MAP_WAVE32_7 | GSOFA_MAP_WG8 | GSOFA_MAP_WG16 | GSOFA_MAP_BYTE |
                                               GSOFA_LEVEL_ORDER | GSOFA_NO_LINE95)) == 0;
     if (eng.plan.window <= 0) eng.plan.window = auto_window(rows);
     if (eng.plan.flags & GSOFA_LEVEL_ORDER) eng.plan.window = (int32_t)std::min<int64_t>(N, 0x7FFFFFFF);

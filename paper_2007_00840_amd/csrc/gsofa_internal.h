@@ -76,7 +76,8 @@ struct TraverseArgs {
     int32_t window;                   // threshold-window span in vertex ids
     uint32_t flags;
     int32_t mapping;                  // 0: one wavefront per source (32-bit labels); 1: 16, 2: 8
-                                      // wavefronts per source; 3: one wavefront, byte states
+                                      // wavefronts per source; 3: one wavefront, byte states;
+                                      // 4: as 0, compiled for seven wavefronts per SIMD
 };
 
 // Row-space description shared by the assembly kernels. With one job,

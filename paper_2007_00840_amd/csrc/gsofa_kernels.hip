@@ -268,11 +268,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t label_rsrc(uint32_t* lab, int6
 // For w > s the first atomic minimum that finds a stale word marks the U entry.
 // The label is read first and the atomic minimum is issued only where it can
 // lower it (an atomic on every edge instead measured 4x slower).
-// Eight wavefronts per SIMD (at most 64 VGPRs; what spills is per-source set-up,
-// outside the level loop; the LDS tables take 15 KB per workgroup of four): more
-// loads in flight than seven (72 VGPRs) or six (80), which were 4 % and 7 % slower
-// on the 64^3 27-point stencil.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_traverse(TraverseArgs a) {
+// Compiled for W wavefronts per SIMD (register budget 512 / W VGPRs; what spills
+// is per-source set-up, outside the level loop; the LDS tables take 15 KB per
+// workgroup of four). W = 8 (mapping 0) keeps the most loads in flight: on the
+// 64^3 27-point stencil seven and six were 4 % and 7 % slower. W = 7 (mapping 4)
+// spills less per source, which pays where sources are many and short: ~4 % on
+// the 1000^2 9-point stencil. The tuner picks between them.
+template <int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) void k_traverse(TraverseArgs a) {
     __shared__ DealTile tiles[kTravWaves];
     __shared__ unsigned long long pushed[kTravWaves][1 << kHashBits];
     __shared__ unsigned long long rdedup[kTravWaves][1 << kDedupBits];
@@ -1539,24 +1542,26 @@ __global__ __launch_bounds__(64 * NW) void k_traverse_wg(TraverseArgs a) {
 
 int32_t traverse_resident_slots(int cus, int mapping) {
     // resident blocks per CU, queried once per mapping
-    static std::atomic<int> known[4] = {{-1}, {-1}, {-1}, {-1}};
-    if (mapping >= 0 && mapping < 4) {
+    static std::atomic<int> known[5] = {{-1}, {-1}, {-1}, {-1}, {-1}};
+    const bool wave_map = mapping == 0 || mapping == 3 || mapping == 4;
+    if (mapping >= 0 && mapping < 5) {
         const int b = known[mapping].load();
-        if (b > 0) return b * ((mapping == 0 || mapping == 3) ? kTravWaves : 1) * cus;
+        if (b > 0) return b * (wave_map ? kTravWaves : 1) * cus;
     }
     int blocks = 0;
     hipError_t e;
     if (mapping == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse8, 64 * kTravWaves, 0);
     else if (mapping == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse_wg<16>, 64 * 16, 0);
     else if (mapping == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse_wg<8>, 64 * 8, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse, 64 * kTravWaves, 0);
+    else if (mapping == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse<7>, 64 * kTravWaves, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse<8>, 64 * kTravWaves, 0);
     if (e != hipSuccess || blocks <= 0) {
         (void)hipGetLastError();
         blocks = 1;
-    } else if (mapping >= 0 && mapping < 4) {
+    } else if (mapping >= 0 && mapping < 5) {
         known[mapping].store(blocks);
     }
-    return blocks * ((mapping == 0 || mapping == 3) ? kTravWaves : 1) * cus;
+    return blocks * (wave_map ? kTravWaves : 1) * cus;
 }
 
 hipError_t launch_traverse(const TraverseArgs& a, hipStream_t st) {
@@ -1568,9 +1573,12 @@ hipError_t launch_traverse(const TraverseArgs& a, hipStream_t st) {
     } else if (a.mapping == 3) {
         const int blocks = (a.nslots + kTravWaves - 1) / kTravWaves;
         hipLaunchKernelGGL(k_traverse8, dim3(blocks), dim3(64 * kTravWaves), 0, st, a);
+    } else if (a.mapping == 4) {
+        const int blocks = (a.nslots + kTravWaves - 1) / kTravWaves;
+        hipLaunchKernelGGL(k_traverse<7>, dim3(blocks), dim3(64 * kTravWaves), 0, st, a);
     } else {
         const int blocks = (a.nslots + kTravWaves - 1) / kTravWaves;
-        hipLaunchKernelGGL(k_traverse, dim3(blocks), dim3(64 * kTravWaves), 0, st, a);
+        hipLaunchKernelGGL(k_traverse<8>, dim3(blocks), dim3(64 * kTravWaves), 0, st, a);
     }
     return hipGetLastError();
 }

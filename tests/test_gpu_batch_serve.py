@@ -56,7 +56,7 @@ def test_batch_equals_single_calls_and_mixed_sizes(g):
             synth.batch_member(8)]
     empty = (0, np.zeros(1, dtype=np.int32), np.zeros(0, dtype=np.int32))
     args = [(m.n, m.row_ptr, m.col_idx) for m in mats] + [empty]
-    for flags in (0, 0x40, 0x100, 0x800):
+    for flags in (0, 0x40, 0x100, 0x800, 0x1000):
         res = g.batch(args, flags=flags)
         for m, r in zip(mats, res):
             assert same_result(r, g.symbolic(m.n, m.row_ptr, m.col_idx))

@@ -111,7 +111,7 @@ def test_edge_sizes(g):
     assert r.nnz_u == n and r.nnz_l == 0 and r.nsuper == n and r.fills == 0
 
 
-@pytest.mark.parametrize("mapping", [0x40, 0x80, 0x100, 0x800])
+@pytest.mark.parametrize("mapping", [0x40, 0x80, 0x100, 0x800, 0x1000])
 @pytest.mark.parametrize("name", ["dense", "arrow_first", "arrow_last", "tril", "triu"])
 def test_closed_forms_on_gpu(g, name, mapping):
     n = 300
@@ -176,6 +176,7 @@ def test_shared_targets_in_one_round(g, case):
     ref = run_ref(n, rp, ci)
     assert_same(g.symbolic(n, rp, ci, window=window), ref)
     assert_same(g.symbolic(n, rp, ci, window=window, flags=0x800), ref)
+    assert_same(g.symbolic(n, rp, ci, window=window, flags=0x1000), ref)
 
 
 def test_full_rows_span_several_sort_chunks(g):
@@ -213,6 +214,7 @@ def test_full_rows_span_several_sort_chunks(g):
     {"flags": 0x800}, {"flags": 0x800, "window": 1}, {"flags": 0x800, "window": 3},
     {"flags": 0x800, "window": 253}, {"flags": 0x800, "window": 200, "concurrent_sources": 5},
     {"flags": 0x800 | 0x20}, {"flags": 0x800 | 0x10},
+    {"flags": 0x1000}, {"flags": 0x1000, "window": 3}, {"flags": 0x1000, "concurrent_sources": 7},
 ], ids=str)
 def test_knobs_do_not_change_results(g, kw):
     m = synth.stencil(27, (11, 10, 9), nd=True, seed=21)
