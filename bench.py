@@ -312,7 +312,7 @@ def bench_serve(g, synth, cap_s, low_rate):
 
 
 # traversal kernel launched for each mapping code reported in the stats
-KERNEL_OF_MAPPING = {3: "k_traverse8", 0: "k_traverse", 4: "k_traverse<7>", 2: "k_traverse_wg<8>",
+KERNEL_OF_MAPPING = {3: "k_traverse8", 0: "k_traverse<8>", 4: "k_traverse<7>", 2: "k_traverse_wg<8>",
                      1: "k_traverse_wg<16>"}
 
 
@@ -426,10 +426,10 @@ def main():
                    "max_supernode": 128, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": recorded_traffic(KERNEL_OF_MAPPING.get(stats[-1]["mapping"], "k_traverse"),
+                     "traffic": recorded_traffic(KERNEL_OF_MAPPING.get(stats[-1]["mapping"], "k_traverse<8>"),
                                                  stats[-1]["mapping"], stats[-1]["window"],
                                                  stats[-1]["concurrent_sources"]),
-                     "kernel": KERNEL_OF_MAPPING.get(stats[-1]["mapping"], "k_traverse"),
+                     "kernel": KERNEL_OF_MAPPING.get(stats[-1]["mapping"], "k_traverse<8>"),
                      "bytes_per_unit": BYTES_PER_EDGE,
                      "unit_count": e_alg, "kernel_ms": round(t_trav, 3)},
         "cpu_baseline": base,
