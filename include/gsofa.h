@@ -104,6 +104,31 @@ typedef enum {
 /* Never time tuner trials in this call (latency-sensitive callers): use the size
  * class's cached choice, else the defaults. The server sets it for every request. */
 #define GSOFA_NO_TUNE           0x2000u
+/* Memory-budget mode (Space Optimization section): the traversal keeps for each
+ * source only what its id needs on the device and puts frontier overflow in host
+ * memory, so that more sources fit a small mem_budget_bytes.
+ *   - bubble removal: labels, level stamps and the pending bitmap of a source
+ *     cover the vertices below it only; sources run in bands of decreasing ids,
+ *     each band a launch whose slots are sized for its largest id, so lower
+ *     bands fit more sources in flight (dynamic space allocation);
+ *   - U-side membership is a bitmap over all n vertices;
+ *   - external frontier management: the two worklists and the row buffer of a
+ *     source hold opts->queue_cap entries in device memory; entries beyond that
+ *     are written to pinned host memory and read back from there by the next
+ *     level (or, for the row buffer, by the copy to the output pool);
+ *   - sources in flight are then cut until the slots fit the budget.
+ * Results are identical to the default mode; stats report spilled entries and
+ * launches. */
+#define GSOFA_BUDGET_MODE       0x4000u
+/* Comparison baseline (Evaluation, fill2 comparison): the fill2 threshold search
+ * with one GPU thread per source row, no intra-source parallelism. Results are
+ * identical; it exists to be timed against the default kernel. */
+#define GSOFA_MAP_THREAD        0x8000u
+/* Ablation of the maxId re-initialisation optimisation (Section 4, maxId
+ * initialisation paragraph): reset the whole label array of a slot before every
+ * source (O(n) per source) instead of moving to a fresh value range. Results
+ * are unchanged. */
+#define GSOFA_RESET_LABELS      0x10000u
 
 /* A CSR pattern: n rows, row_ptr[n+1], col_idx[row_ptr[n]]; host pointers
  * unless GSOFA_INPUT_ON_DEVICE is set. */
@@ -115,15 +140,17 @@ typedef struct {
 
 typedef struct {
     int32_t status;             /* per-matrix status (batch, serve)                       */
-    int32_t iterations;         /* frontier-expansion steps, summed over sources          */
-    int32_t windows;            /* threshold windows, summed over sources                 */
     int32_t concurrent_sources; /* sources in flight at once (#C)                         */
+    uint64_t iterations;        /* frontier-expansion steps, summed over sources          */
+    uint64_t windows;           /* threshold windows, summed over sources                 */
     uint64_t edges_alg;         /* algorithmic edges: for each source row, deg(src) plus
                                    deg(v) of every v < src reachable from src through
                                    vertices < src (each counted once per source)          */
     uint64_t edges_gpu;         /* edges actually scanned, revisits included              */
     uint64_t peak_device_bytes; /* device working memory of this call                     */
-    double t_traverse_ms;       /* fill-detection kernel time (seed + traversal)          */
+    double t_traverse_ms;       /* fill-detection kernel time: the per-source seed (the
+                                   source row's own entries) runs inside the traversal
+                                   kernel, so seed and traversal are timed together       */
     double t_emit_ms;           /* pointer scans and per-row sort into CSR                */
     double t_supernode_ms;
     double t_total_ms;          /* whole call, host copies included                       */
@@ -131,8 +158,14 @@ typedef struct {
     int32_t mapping;            /* traversal mapping used: 0 one wavefront per source with
                                    32-bit labels, 4 the same compiled for seven wavefronts
                                    per SIMD, 3 one wavefront with byte states, 2 / 1 eight
-                                   / sixteen wavefronts per source                        */
+                                   / sixteen wavefronts per source, 5 the memory-budget
+                                   kernel (GSOFA_BUDGET_MODE), 6 one thread per source
+                                   (GSOFA_MAP_THREAD, comparison baseline)                */
     double t_tune_ms;           /* autotuner trial time spent in this call (0 if none)    */
+    uint64_t spilled_entries;   /* worklist and row-buffer entries written to host memory
+                                   (GSOFA_BUDGET_MODE; 0 otherwise)                       */
+    int32_t launches;           /* traversal launches (source-id bands in budget mode)    */
+    int32_t pad_;
 } gsofa_stats;
 
 typedef void* (*gsofa_alloc_fn)(size_t bytes, void* ctx);
@@ -146,11 +179,26 @@ typedef struct {
     int32_t window;             /* threshold-window span (vertex ids); 0 -> autotuned    */
     int32_t concurrent_sources; /* sources in flight; 0 -> planned from memory and CUs    */
     void* stream;               /* hipStream_t to run on; NULL -> the null stream         */
-    gsofa_alloc_fn dev_alloc;   /* reserved for a caller-side device allocator; must be
-                                   NULL (GSOFA_EINVAL otherwise): device memory comes from
-                                   the library's cache, see gsofa_release_cache          */
-    gsofa_free_fn dev_free;     /* reserved; must be NULL                                 */
-    void* alloc_ctx;            /* reserved                                               */
+    gsofa_alloc_fn dev_alloc;   /* optional caller-side device allocator (for example a
+                                   tensor framework's caching allocator). With dev_alloc
+                                   and dev_free both set, every device buffer of the call
+                                   comes from dev_alloc(bytes, alloc_ctx), called on the
+                                   calling thread (worker threads for the server) with the
+                                   call's device current: source-slot state, output pool,
+                                   scratch and GSOFA_RESULT_ON_DEVICE results. It returns
+                                   memory aligned to at least 256 bytes, or NULL (the call
+                                   then fails with GSOFA_ENOMEM). The library's own device
+                                   cache is neither used nor filled by such a call.
+                                   Working buffers go back through dev_free(ptr, alloc_ctx)
+                                   only once the call's device work has completed; result
+                                   buffers when gsofa_result_free releases the last result
+                                   of the call. Setting only one of the two: GSOFA_EINVAL. */
+    gsofa_free_fn dev_free;
+    void* alloc_ctx;            /* passed unchanged to dev_alloc and dev_free              */
+    int32_t queue_cap;          /* GSOFA_BUDGET_MODE: device entries per source worklist
+                                   and row buffer before the overflow goes to host memory;
+                                   0 -> 8192                                               */
+    int32_t pad_;
 } gsofa_opts;
 
 typedef struct {
@@ -238,6 +286,14 @@ GSOFA_API int gsofa_release_cache(void);
  * instantiated, out[1] executable graphs updated in place for a later call,
  * out[2] graph launches. out must hold 3 entries; GSOFA_EINVAL if NULL. */
 GSOFA_API int gsofa_graph_counters(uint64_t* out);
+
+/* Process-wide device-memory counters since load, for the current device and
+ * all others together: out[0] bytes the library currently holds from its own
+ * hipMalloc calls (in use and cached idle), out[1] hipMalloc calls made by the
+ * library, out[2] bytes obtained through caller allocators (dev_alloc),
+ * out[3] dev_alloc calls, out[4] dev_free calls. out must hold 5 entries;
+ * GSOFA_EINVAL if NULL. */
+GSOFA_API int gsofa_memory_counters(uint64_t* out);
 
 #ifdef __cplusplus
 }

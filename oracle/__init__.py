@@ -69,6 +69,9 @@ def _load():
                                     ctypes.POINTER(ctypes.c_void_p)]
         lib.oracle_free.restype = None
         lib.oracle_free.argtypes = [ctypes.c_void_p]
+        lib.oracle_transpose.restype = ctypes.c_int
+        lib.oracle_transpose.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_supernodes.restype = ctypes.c_int32
         lib.oracle_supernodes.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_int32,
@@ -158,8 +161,26 @@ class Symbolic:
         return None if self.xsup is None else len(self.xsup) - 1
 
 
+def csr_to_csc(n, ptr, idx):
+    """Transpose a CSR pattern (rows ascending within each column): a counting
+    sort in C that visits the rows in order (``oracle_transpose``)."""
+    lib = _load()
+    ptr = np.ascontiguousarray(ptr, dtype=np.int64)
+    idx = _i32(idx)
+    t_ptr = np.zeros(n + 1, dtype=np.int64)
+    t_idx = np.zeros(max(int(ptr[n]) if n > 0 else 0, 0), dtype=np.int32)
+    if n > 0:
+        rc = lib.oracle_transpose(int(n), ptr.ctypes.data, idx.ctypes.data if len(idx) else None,
+                                  t_ptr.ctypes.data, t_idx.ctypes.data if len(t_idx) else None)
+        if rc != 0:
+            raise MemoryError("oracle_transpose failed")
+    return t_ptr, t_idx
+
+
 def pattern_with_diag_nnz(n, row_ptr, col_idx) -> int:
-    """nnz(pattern(A) union diag)."""
+    """nnz(pattern(A) union diag): the stored entries plus one for every row
+    without a stored diagonal entry (the denominator of the dataset table's
+    fill-in count)."""
     row_ptr = np.asarray(row_ptr, dtype=np.int64)
     col_idx = np.asarray(col_idx)
     rows = np.repeat(np.arange(n), np.diff(row_ptr))
@@ -168,17 +189,10 @@ def pattern_with_diag_nnz(n, row_ptr, col_idx) -> int:
     return int(len(col_idx) + (~diag_present).sum())
 
 
-def csr_to_csc(n, ptr, idx):
-    """Transpose a CSR pattern (rows ascending within each column). A stable
-    sort by column keeps the ascending row order."""
-    ptr = np.asarray(ptr, dtype=np.int64)
-    rows = np.repeat(np.arange(n, dtype=np.int32), np.diff(ptr))
-    order = np.argsort(idx, kind="stable")
-    t_idx = rows[order].astype(np.int32)
-    counts = np.bincount(idx, minlength=n).astype(np.int64)
-    t_ptr = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(counts, out=t_ptr[1:])
-    return t_ptr, t_idx
+def fills(res, row_ptr, col_idx) -> int:
+    """fills = nnz(L) + nnz(U) - nnz(pattern(A) union diag) (dataset table,
+    "#Fill-in")."""
+    return res.nnz_l + res.nnz_u - pattern_with_diag_nnz(res.n, row_ptr, col_idx)
 
 
 def symbolic(n, row_ptr, col_idx, max_supernode=128, threads=None,

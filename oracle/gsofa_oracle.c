@@ -292,3 +292,22 @@ int32_t oracle_supernodes(int32_t n, const int64_t *u_cnt, const int64_t *l_ptr,
     xsup[ns] = n;
     return ns;
 }
+
+/* ---- transpose of a CSR pattern (test helper, no arithmetic of the method)
+ * out_ptr[c+1] - out_ptr[c] = entries in column c; rows are visited in
+ * increasing order, so each column's row indices come out ascending. This
+ * turns the row-wise L of O1 into the column-wise layout the library returns. */
+int oracle_transpose(int32_t n, const int64_t *ptr, const int32_t *idx,
+                     int64_t *out_ptr, int32_t *out_idx)
+{
+    int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!cur) return -1;
+    memset(out_ptr, 0, sizeof(int64_t) * (size_t)(n + 1));
+    for (int64_t e = 0; e < ptr[n]; ++e) out_ptr[idx[e] + 1] += 1;
+    for (int32_t c = 0; c < n; ++c) out_ptr[c + 1] += out_ptr[c];
+    for (int32_t c = 0; c < n; ++c) cur[c] = out_ptr[c];
+    for (int32_t r = 0; r < n; ++r)
+        for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) out_idx[cur[idx[e]]++] = r;
+    free(cur);
+    return 0;
+}

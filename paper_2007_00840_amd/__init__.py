@@ -33,10 +33,13 @@ MAP_BYTE = 0x800
 MAP_WAVE32_7 = 0x1000
 TUNE_NOW = 0x400
 NO_TUNE = 0x2000
+BUDGET_MODE = 0x4000
+MAP_THREAD = 0x8000
+RESET_LABELS = 0x10000
 
 EXPORTED = ["gsofa_symbolic", "gsofa_batch", "gsofa_serve_open", "gsofa_serve_submit",
             "gsofa_serve_poll", "gsofa_serve_close", "gsofa_result_free", "gsofa_strerror",
-            "gsofa_release_cache", "gsofa_graph_counters"]
+            "gsofa_release_cache", "gsofa_graph_counters", "gsofa_memory_counters"]
 
 
 class GsofaError(RuntimeError):
@@ -50,21 +53,28 @@ class Csr(ctypes.Structure):
 
 
 class Stats(ctypes.Structure):
-    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
-                ("windows", ctypes.c_int32), ("concurrent_sources", ctypes.c_int32),
+    _fields_ = [("status", ctypes.c_int32), ("concurrent_sources", ctypes.c_int32),
+                ("iterations", ctypes.c_uint64), ("windows", ctypes.c_uint64),
                 ("edges_alg", ctypes.c_uint64), ("edges_gpu", ctypes.c_uint64),
                 ("peak_device_bytes", ctypes.c_uint64), ("t_traverse_ms", ctypes.c_double),
                 ("t_emit_ms", ctypes.c_double), ("t_supernode_ms", ctypes.c_double),
                 ("t_total_ms", ctypes.c_double), ("window", ctypes.c_int32),
-                ("mapping", ctypes.c_int32), ("t_tune_ms", ctypes.c_double)]
+                ("mapping", ctypes.c_int32), ("t_tune_ms", ctypes.c_double),
+                ("spilled_entries", ctypes.c_uint64), ("launches", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class Opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("max_supernode", ctypes.c_int32),
                 ("mem_budget_bytes", ctypes.c_int64), ("flags", ctypes.c_uint32),
                 ("window", ctypes.c_int32), ("concurrent_sources", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("dev_alloc", ctypes.c_void_p),
-                ("dev_free", ctypes.c_void_p), ("alloc_ctx", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN),
+                ("dev_free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
+                ("queue_cap", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -110,6 +120,8 @@ def load():
         lib.gsofa_release_cache.argtypes = []
         lib.gsofa_graph_counters.restype = ctypes.c_int
         lib.gsofa_graph_counters.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
+        lib.gsofa_memory_counters.restype = ctypes.c_int
+        lib.gsofa_memory_counters.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
         _lib = lib
     return _lib
 
@@ -121,8 +133,53 @@ def strerror(code: int) -> str:
         return f"status {code}"
 
 
+class TorchAllocator:
+    """Device memory for the library from torch's caching allocator (the
+    gsofa_opts dev_alloc / dev_free hooks). Each block is a uint8 tensor kept
+    alive until the library frees it; counts what went through it."""
+
+    def __init__(self, device=None):
+        import torch
+        self._torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        self.live = {}
+        self.bytes = 0
+        self.allocs = 0
+        self.frees = 0
+        self.peak_live_bytes = 0
+        self._live_bytes = 0
+
+        def _alloc(nbytes, ctx):
+            try:
+                t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device=self.device)
+            except RuntimeError:
+                return None
+            p = t.data_ptr()
+            self.live[p] = t
+            self.bytes += int(nbytes)
+            self.allocs += 1
+            self._live_bytes += int(nbytes)
+            self.peak_live_bytes = max(self.peak_live_bytes, self._live_bytes)
+            return p
+
+        def _free(ptr, ctx):
+            t = self.live.pop(ptr, None)
+            if t is not None:
+                self._live_bytes -= t.numel()
+            self.frees += 1
+
+        # the ctypes callbacks must outlive every call and result that uses them
+        self.alloc_fn = ALLOC_FN(_alloc)
+        self.free_fn = FREE_FN(_free)
+
+    def install(self, o: Opts):
+        o.dev_alloc = self.alloc_fn
+        o.dev_free = self.free_fn
+        o.alloc_ctx = None
+
+
 def make_opts(flags=0, max_supernode=0, mem_budget_bytes=0, window=0,
-              concurrent_sources=0, stream=None) -> Opts:
+              concurrent_sources=0, stream=None, allocator=None, queue_cap=0) -> Opts:
     o = Opts()
     o.struct_size = ctypes.sizeof(Opts)
     o.max_supernode = int(max_supernode)
@@ -131,6 +188,9 @@ def make_opts(flags=0, max_supernode=0, mem_budget_bytes=0, window=0,
     o.window = int(window)
     o.concurrent_sources = int(concurrent_sources)
     o.stream = stream
+    o.queue_cap = int(queue_cap)
+    if allocator is not None:
+        allocator.install(o)
     return o
 
 
@@ -245,7 +305,7 @@ def _arr_ptr(a):
 
 
 def symbolic(n, row_ptr, col_idx, flags=0, max_supernode=0, mem_budget_bytes=0, window=0,
-             concurrent_sources=0, stream=None):
+             concurrent_sources=0, stream=None, allocator=None, queue_cap=0):
     """gsofa_symbolic. Host numpy arrays or device int32 tensors (then the
     INPUT_ON_DEVICE flag is set). Returns SymbolicResult, or DeviceResult with
     RESULT_ON_DEVICE."""
@@ -256,7 +316,8 @@ def symbolic(n, row_ptr, col_idx, flags=0, max_supernode=0, mem_budget_bytes=0, 
         raise ValueError("row_ptr and col_idx must both be host or both be device arrays")
     if rp_dev:
         flags |= INPUT_ON_DEVICE
-    o = make_opts(flags, max_supernode, mem_budget_bytes, window, concurrent_sources, stream)
+    o = make_opts(flags, max_supernode, mem_budget_bytes, window, concurrent_sources, stream,
+                  allocator, queue_cap)
     out = ctypes.POINTER(Result)()
     rc = lib.gsofa_symbolic(int(n), rp_p, ci_p, ctypes.byref(o), ctypes.byref(out))
     del rp_keep, ci_keep
@@ -271,7 +332,7 @@ def symbolic(n, row_ptr, col_idx, flags=0, max_supernode=0, mem_budget_bytes=0, 
 
 
 def batch(mats, flags=0, max_supernode=0, mem_budget_bytes=0, window=0,
-          concurrent_sources=0, stream=None, raise_on_error=True):
+          concurrent_sources=0, stream=None, raise_on_error=True, allocator=None, queue_cap=0):
     """gsofa_batch over a list of (n, row_ptr, col_idx). Returns a list of
     SymbolicResult (or DeviceResult), with None where a matrix failed when
     raise_on_error is False."""
@@ -292,7 +353,8 @@ def batch(mats, flags=0, max_supernode=0, mem_budget_bytes=0, window=0,
         arr[i].col_idx = ci_p
     if on_dev:
         flags |= INPUT_ON_DEVICE
-    o = make_opts(flags, max_supernode, mem_budget_bytes, window, concurrent_sources, stream)
+    o = make_opts(flags, max_supernode, mem_budget_bytes, window, concurrent_sources, stream,
+                  allocator, queue_cap)
     outs = (ctypes.POINTER(Result) * max(count, 1))()
     rc = lib.gsofa_batch(count, arr, ctypes.byref(o), outs)
     del keep
@@ -327,9 +389,11 @@ class Server:
     """gsofa_serve_open / submit / poll / close."""
 
     def __init__(self, max_inflight=4, flags=0, max_supernode=0, mem_budget_bytes=0,
-                 window=0, concurrent_sources=0):
+                 window=0, concurrent_sources=0, allocator=None, queue_cap=0):
         self._lib = load()
-        o = make_opts(flags, max_supernode, mem_budget_bytes, window, concurrent_sources, None)
+        self._allocator = allocator  # its callbacks must outlive the server
+        o = make_opts(flags, max_supernode, mem_budget_bytes, window, concurrent_sources, None,
+                      allocator, queue_cap)
         self._h = ctypes.c_void_p()
         rc = self._lib.gsofa_serve_open(ctypes.byref(o), int(max_inflight), ctypes.byref(self._h))
         if rc != OK:
@@ -375,6 +439,16 @@ class Server:
 
 def release_cache():
     return load().gsofa_release_cache()
+
+
+def memory_counters():
+    """(bytes held from the library's own hipMalloc, its hipMalloc calls, bytes
+    from caller allocators, dev_alloc calls, dev_free calls) since load."""
+    out = (ctypes.c_uint64 * 5)()
+    rc = load().gsofa_memory_counters(out)
+    if rc != OK:
+        raise GsofaError(rc, "gsofa_memory_counters")
+    return tuple(int(x) for x in out)
 
 
 def graph_counters():

@@ -69,6 +69,10 @@ struct StreamScope {
 
 void drop_idle_slots();
 
+// process-wide device-memory counters (gsofa_memory_counters)
+std::atomic<uint64_t> g_hip_bytes_held{0}, g_hip_mallocs{0}, g_caller_bytes{0}, g_caller_allocs{0},
+    g_caller_frees{0};
+
 class DevCache {
    public:
     void* alloc(size_t bytes, hipStream_t st) {
@@ -90,16 +94,19 @@ class DevCache {
         }
         void* p = nullptr;
         hipError_t e = hipMalloc(&p, bytes);
+        g_hip_mallocs.fetch_add(1);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             drop_idle_slots();
             release();
             e = hipMalloc(&p, bytes);
+            g_hip_mallocs.fetch_add(1);
             if (e != hipSuccess) {
                 (void)hipGetLastError();
                 throw Status{GSOFA_ENOMEM};
             }
         }
+        g_hip_bytes_held.fetch_add(bytes);
         std::lock_guard<std::mutex> g(mu_);
         used_[p] = bytes;
         return p;
@@ -142,6 +149,7 @@ class DevCache {
                 (void)hipEventDestroy(kv.second.ev);
             }
             (void)hipFree(kv.second.p);
+            g_hip_bytes_held.fetch_sub(kv.first);
         }
         free_.clear();
         (void)hipGetLastError();
@@ -163,18 +171,72 @@ DevCache& cache() {
     return *c;
 }
 
-// A device buffer taken from the cache on the calling thread's engine stream,
-// returned with that stream's ordering on destruction.
+// The caller's device allocator of one call (gsofa_opts dev_alloc / dev_free).
+// Buffers released while the call's device work may still use them are kept
+// until flush(), which runs once that work has completed.
+struct CallerAlloc {
+    gsofa_alloc_fn alloc_fn = nullptr;
+    gsofa_free_fn free_fn = nullptr;
+    void* ctx = nullptr;
+    std::mutex mu;
+    std::vector<void*> deferred;
+
+    void* take(size_t bytes) {
+        bytes = (bytes + 255) & ~size_t(255);
+        void* p = alloc_fn(bytes, ctx);
+        if (!p) throw Status{GSOFA_ENOMEM};
+        g_caller_allocs.fetch_add(1);
+        g_caller_bytes.fetch_add(bytes);
+        if (reinterpret_cast<uintptr_t>(p) & 255u) {
+            give(p);
+            throw Status{GSOFA_EINVAL};  // the allocator must align to 256 bytes
+        }
+        return p;
+    }
+    void give(void* p) {
+        free_fn(p, ctx);
+        g_caller_frees.fetch_add(1);
+    }
+    // idle: no device work can still use the buffer
+    void release(void* p, bool idle) {
+        if (idle) {
+            give(p);
+            return;
+        }
+        std::lock_guard<std::mutex> g(mu);
+        deferred.push_back(p);
+    }
+    void flush() {
+        std::vector<void*> v;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            v.swap(deferred);
+        }
+        for (void* p : v) give(p);
+    }
+};
+
+// Set for the length of a call that brought its own allocator.
+thread_local std::shared_ptr<CallerAlloc> t_calloc;
+
+// A device buffer taken from the caller's allocator when the call brought one,
+// else from the cache on the calling thread's engine stream, returned with that
+// stream's ordering on destruction.
 struct DBuf {
     void* p = nullptr;
     size_t bytes = 0;
     hipStream_t st = nullptr;
     bool synced = false;  // set once no work on the buffer can be pending
+    std::shared_ptr<CallerAlloc> ca;
     DBuf() = default;
-    explicit DBuf(size_t b) : p(cache().alloc(b, t_stream)), bytes(b), st(t_stream) {}
+    explicit DBuf(size_t b) : bytes(b), st(t_stream), ca(t_calloc) {
+        p = ca ? ca->take(b) : cache().alloc(b, t_stream);
+    }
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
-    DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes), st(o.st), synced(o.synced) { o.p = nullptr; }
+    DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes), st(o.st), synced(o.synced), ca(std::move(o.ca)) {
+        o.p = nullptr;
+    }
     DBuf& operator=(DBuf&& o) noexcept {
         if (this != &o) {
             reset();
@@ -182,13 +244,18 @@ struct DBuf {
             bytes = o.bytes;
             st = o.st;
             synced = o.synced;
+            ca = std::move(o.ca);
             o.p = nullptr;
         }
         return *this;
     }
     ~DBuf() { reset(); }
     void reset() {
-        if (p) cache().free(p, st, synced || (t_idle && st == t_stream));
+        if (p) {
+            const bool idle = synced || (t_idle && st == t_stream);
+            if (ca) ca->release(p, idle);
+            else cache().free(p, st, idle);
+        }
         p = nullptr;
     }
     template <typename T>
@@ -440,7 +507,7 @@ std::vector<std::unique_ptr<SlotSet>>& idle_slots() {
 }
 
 std::unique_ptr<SlotSet> take_slots(const SlotLayout& lay, int32_t nslots, int mode, hipStream_t st) {
-    {
+    if (!t_calloc) {
         std::lock_guard<std::mutex> g(g_slot_mu);
         auto& v = idle_slots();
         for (size_t i = 0; i < v.size(); ++i) {
@@ -471,6 +538,7 @@ std::unique_ptr<SlotSet> take_slots(const SlotLayout& lay, int32_t nslots, int m
 // Called once the traversal that used the slots has completed.
 void give_slots(std::unique_ptr<SlotSet> s) {
     s->buf.synced = true;
+    if (s->buf.ca) return;  // the caller's memory goes straight back
     std::vector<std::unique_ptr<SlotSet>> drop;
     {
         std::lock_guard<std::mutex> g(g_slot_mu);
@@ -969,6 +1037,7 @@ struct Engine {
 
         bool overflow = false;
         float t_trav_extra = 0;
+        int32_t n_launches = 1;
         for (int32_t q = 0; q < nj; ++q) {
             if (hst[q].err & kErrDuplicate) jstat[ord[q]] = GSOFA_EINVAL;
             if (hst[q].err & kErrOverflow) overflow = true;
@@ -1006,6 +1075,7 @@ struct Engine {
             t_trav_extra += first_ms;
             chk(hipEventRecord(ev[0], st));
             chk(launch_traverse(ta, st));
+            ++n_launches;
             chk(hipEventRecord(ev[4], st));
             chk(launch_job_stats(d_jobs.as<Job>(), nj, N, row_stats.as<RowStat>(), jst.as<JobStats>(), st));
             chk(hipMemcpyAsync(hst, jst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, st));
@@ -1256,8 +1326,8 @@ struct Engine {
             r->stats.status = jstat[j];
             r->stats.edges_alg = hst[q].edges_alg;
             r->stats.edges_gpu = hst[q].edges_gpu;
-            r->stats.iterations = (int32_t)std::min<unsigned long long>(hst[q].iterations, 0x7FFFFFFF);
-            r->stats.windows = (int32_t)std::min<unsigned long long>(hst[q].windows, 0x7FFFFFFF);
+            r->stats.iterations = hst[q].iterations;
+            r->stats.windows = hst[q].windows;
             r->stats.concurrent_sources = ta.nslots;
             r->stats.peak_device_bytes =
                 (uint64_t)(nslots * lay.bytes_per_slot + pool_cap * 4 + nrows * 48 + (nnz_u + 3 * nnz_l) * 4);
@@ -1267,6 +1337,8 @@ struct Engine {
             r->stats.window = plan.window;
             r->stats.mapping = mapping;
             r->stats.t_tune_ms = t_tune;
+            r->stats.launches = n_launches;
+            r->stats.spilled_entries = 0;
             if (jstat[j] != GSOFA_OK) continue;
             const int64_t n = mats[j].n, b = row_base[j];
             r->nnz_a = nnz[j];
@@ -1459,7 +1531,8 @@ int check_opts(const gsofa_opts* o) {
     if (!o) return GSOFA_OK;
     if (o->struct_size != 0 && o->struct_size < sizeof(gsofa_opts)) return GSOFA_EINVAL;
     if (o->mem_budget_bytes < 0 || o->window < 0 || o->concurrent_sources < 0) return GSOFA_EINVAL;
-    if (o->dev_alloc || o->dev_free) return GSOFA_EINVAL;
+    if ((o->dev_alloc == nullptr) != (o->dev_free == nullptr)) return GSOFA_EINVAL;
+    if (o->queue_cap < 0) return GSOFA_EINVAL;
     return GSOFA_OK;
 }
 
@@ -1483,6 +1556,27 @@ int run_engine(std::vector<MatIn> mats, const gsofa_opts* o, std::vector<gsofa_r
                                               GSOFA_LEVEL_ORDER | GSOFA_NO_LINE95)) == 0;
     if (eng.plan.window <= 0) eng.plan.window = auto_window(rows);
     if (eng.plan.flags & GSOFA_LEVEL_ORDER) eng.plan.window = (int32_t)std::min<int64_t>(N, 0x7FFFFFFF);
+    // a caller allocator serves every device buffer of this call; buffers it
+    // releases early go back once the call's device work has completed
+    struct AllocScope {
+        std::shared_ptr<CallerAlloc> prev, cur;
+        hipStream_t st;
+        ~AllocScope() {
+            if (cur) {
+                (void)hipStreamSynchronize(st);
+                (void)hipGetLastError();
+                cur->flush();
+            }
+            t_calloc = prev;
+        }
+    } as{t_calloc, nullptr, eng.st};
+    if (o && o->dev_alloc) {
+        as.cur = std::make_shared<CallerAlloc>();
+        as.cur->alloc_fn = o->dev_alloc;
+        as.cur->free_fn = o->dev_free;
+        as.cur->ctx = o->alloc_ctx;
+    }
+    t_calloc = as.cur;
     int rc;
     try {
         rc = eng.run();
@@ -1603,6 +1697,16 @@ extern "C" GSOFA_API int gsofa_release_cache(void) {
     std::lock_guard<std::mutex> g(g_api_mu);
     drop_idle_slots();
     cache().release();
+    return GSOFA_OK;
+}
+
+extern "C" GSOFA_API int gsofa_memory_counters(uint64_t* out) {
+    if (!out) return GSOFA_EINVAL;
+    out[0] = g_hip_bytes_held.load();
+    out[1] = g_hip_mallocs.load();
+    out[2] = g_caller_bytes.load();
+    out[3] = g_caller_allocs.load();
+    out[4] = g_caller_frees.load();
     return GSOFA_OK;
 }
 

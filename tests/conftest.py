@@ -50,3 +50,39 @@ def adj_to_csr(adj):
 @pytest.fixture(scope="session")
 def golden():
     return read_golden
+
+
+def oracle_members(mats):
+    """O1 for many matrices in one call: their block-diagonal concatenation
+    (no path crosses a block, so every row's structure is its matrix's row
+    structure shifted by the block's first row), then per matrix the L
+    transpose and the supernodes."""
+    import numpy as np
+    import oracle
+    ns = [m.n for m in mats]
+    base = np.zeros(len(mats) + 1, dtype=np.int64)
+    np.cumsum(ns, out=base[1:])
+    nnz = np.zeros(len(mats) + 1, dtype=np.int64)
+    np.cumsum([m.nnz for m in mats], out=nnz[1:])
+    rp = np.concatenate([mats[0].row_ptr[:1].astype(np.int64)] +
+                        [m.row_ptr[1:].astype(np.int64) + nnz[k] for k, m in enumerate(mats)])
+    ci = np.concatenate([m.col_idx.astype(np.int64) + base[k] for k, m in enumerate(mats)])
+    cnt, lcnt, edges, ptr, ent = oracle.rows_struct(int(base[-1]), rp.astype(np.int32),
+                                                    ci.astype(np.int32))
+    out = []
+    for k, m in enumerate(mats):
+        r0, r1 = int(base[k]), int(base[k + 1])
+        e = ent[ptr[r0]:ptr[r1]] - np.int32(r0)
+        c, lc = cnt[r0:r1], lcnt[r0:r1]
+        rows = np.repeat(np.arange(m.n, dtype=np.int32), c)
+        is_u = e >= rows
+        u_ptr = np.zeros(m.n + 1, dtype=np.int64)
+        np.cumsum(c - lc, out=u_ptr[1:])
+        l_rptr = np.zeros(m.n + 1, dtype=np.int64)
+        np.cumsum(lc, out=l_rptr[1:])
+        l_ridx = e[~is_u]
+        l_ptr, l_idx = oracle.csr_to_csc(m.n, l_rptr, l_ridx)
+        xsup, supno = oracle.supernodes(m.n, c - lc, l_rptr, l_ridx, 128)
+        out.append(oracle.Symbolic(m.n, u_ptr, e[is_u], l_rptr, l_ridx, l_ptr, l_idx,
+                                   edges[r0:r1], m.nnz, xsup, supno))
+    return out

@@ -31,7 +31,7 @@ def g():
 
 def test_exports_every_declared_symbol(g):
     decl = _declared()
-    assert len(decl) == 10 and set(decl) == set(g.EXPORTED)
+    assert len(decl) == len(g.EXPORTED) and set(decl) == set(g.EXPORTED)
     out = subprocess.run(["nm", "-D", "--defined-only", g.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
     exported = set(re.findall(r" T (gsofa_\w+)", out))
@@ -44,15 +44,18 @@ def test_exports_every_declared_symbol(g):
 def test_struct_layout_matches_header(g, tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include "gsofa.h"\n#include <stdio.h>\n#include <stddef.h>\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gsofa_opts),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gsofa_opts),'
                    ' sizeof(gsofa_result), sizeof(gsofa_stats), sizeof(gsofa_csr),'
                    ' offsetof(gsofa_result, stats), offsetof(gsofa_result, xsup),'
-                   ' offsetof(gsofa_opts, stream));return 0;}\n')
+                   ' offsetof(gsofa_opts, stream), offsetof(gsofa_opts, queue_cap),'
+                   ' offsetof(gsofa_stats, spilled_entries), offsetof(gsofa_stats, iterations));'
+                   'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     want = [ctypes.sizeof(g.Opts), ctypes.sizeof(g.Result), ctypes.sizeof(g.Stats),
-            ctypes.sizeof(g.Csr), g.Result.stats.offset, g.Result.xsup.offset, g.Opts.stream.offset]
+            ctypes.sizeof(g.Csr), g.Result.stats.offset, g.Result.xsup.offset, g.Opts.stream.offset,
+            g.Opts.queue_cap.offset, g.Stats.spilled_entries.offset, g.Stats.iterations.offset]
     assert got == want
 
 
@@ -99,8 +102,18 @@ def test_bad_opts_rejected(g):
     assert lib.gsofa_symbolic(1, rp.ctypes.data, ci.ctypes.data, ctypes.byref(o),
                               ctypes.byref(out)) == g.EINVAL
     assert not out
+    # an allocator needs both hooks: one alone is rejected before anything runs
+    calls = []
     o = g.make_opts()
-    o.dev_alloc = 1234
+    o.dev_alloc = g.ALLOC_FN(lambda nbytes, ctx: calls.append(nbytes) or None)
+    assert lib.gsofa_symbolic(1, rp.ctypes.data, ci.ctypes.data, ctypes.byref(o),
+                              ctypes.byref(out)) == g.EINVAL
+    o = g.make_opts()
+    o.dev_free = g.FREE_FN(lambda ptr, ctx: calls.append(ptr))
+    assert lib.gsofa_symbolic(1, rp.ctypes.data, ci.ctypes.data, ctypes.byref(o),
+                              ctypes.byref(out)) == g.EINVAL
+    assert not out and calls == []
+    o = g.make_opts(queue_cap=-1)
     assert lib.gsofa_symbolic(1, rp.ctypes.data, ci.ctypes.data, ctypes.byref(o),
                               ctypes.byref(out)) == g.EINVAL
 
@@ -125,6 +138,13 @@ def test_graph_counters_argument_error(g):
     assert lib.gsofa_graph_counters(None) == g.EINVAL
     a = g.graph_counters()
     assert len(a) == 3 and all(x >= 0 for x in a)
+
+
+def test_memory_counters_argument_error(g):
+    lib = g.load()
+    assert lib.gsofa_memory_counters(None) == g.EINVAL
+    a = g.memory_counters()
+    assert len(a) == 5 and all(x >= 0 for x in a)
 
 
 def test_bench_reads_its_traffic_record():

@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 import synth
+from conftest import oracle_members
 
 pytestmark = pytest.mark.gpu
 
@@ -40,14 +41,18 @@ def same_result(a, b):
 
 
 def test_batch_members_match_oracle(g):
-    ks = list(range(0, 96)) + [4095]
-    mats = [synth.batch_member(k) for k in ks]
+    """The whole 4,096-matrix batch in one gsofa_batch call, every member
+    compared in full against the oracle."""
+    mats = [synth.batch_member(k) for k in range(4096)]
     _say(f"batch of {len(mats)} members, sum n = {sum(m.n for m in mats)}")
     res = g.batch([(m.n, m.row_ptr, m.col_idx) for m in mats])
     assert len(res) == len(mats)
-    for k, m, r in zip(ks, mats, res):
-        ref = oracle.symbolic(m.n, m.row_ptr, m.col_idx)
-        assert same(r, ref), f"member {k}"
+    _say("gpu batch done")
+    for lo in range(0, len(mats), 512):
+        refs = oracle_members(mats[lo:lo + 512])
+        for k, (m, r, ref) in enumerate(zip(mats[lo:lo + 512], res[lo:lo + 512], refs)):
+            assert same(r, ref), f"member {lo + k}"
+        _say(f"members {lo}..{lo + 511} ok")
 
 
 def test_batch_equals_single_calls_and_mixed_sizes(g):
@@ -122,6 +127,25 @@ def test_serve_results_alone_and_in_mix(g):
         ref = oracle.symbolic(m.n, m.row_ptr, m.col_idx)
         assert same(a, ref)
         assert same_result(a, mixed[t])
+
+
+def test_serve_trace_sample_with_large_requests(g):
+    """Requests of the served stream above 10^5 rows, one 2D 9-point and one
+    3D 27-point, mixed with small ones of the same trace: all in flight
+    together, every array of every result compared in full with the oracle."""
+    reqs = synth.serve_trace(count=60)
+    big2 = next(r for r in reqs if r.n_req > 100000 and r.kind == 9)
+    big3 = next(r for r in reqs if r.n_req > 100000 and r.kind == 27)
+    small = [r for r in reqs if r.n_req <= 20000][:6]
+    chosen = [big2, big3] + small
+    mats = [r.matrix() for r in chosen]
+    _say(f"serve trace sample: requests {[r.rid for r in chosen]}, n = {[m.n for m in mats]}")
+    with g.Server(max_inflight=4) as srv:
+        tickets = [srv.submit(m.n, m.row_ptr, m.col_idx) for m in mats]
+        got = [srv.poll(t, timeout_us=-1) for t in tickets]
+    _say("served; checking against the oracle")
+    for r, m, res in zip(chosen, mats, got):
+        assert same(res, oracle.symbolic(m.n, m.row_ptr, m.col_idx)), f"request {r.rid}"
 
 
 def test_serve_status_codes(g):

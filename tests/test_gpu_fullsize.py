@@ -1,9 +1,9 @@
 """Full-size parity on the 2D (1000x1000 9-point) and 3D (64^3 27-point)
 workloads, in the launch configuration bench.py times (automatic mapping and
-slots, device-resident input): U rows, supernodes and every total are compared
-in full against the oracle; L columns are compared on a sample through the
-transpose duality filled(A^T) = filled(A)^T (column k of L(A) is the strict
-upper part of row k of U(A^T))."""
+slots, device-resident input): every output array -- U in CSR, L in CSC,
+supernodes -- and every total is compared in full against the oracle. L's
+column layout comes from the oracle's rows through its counting-sort
+transpose."""
 import sys
 
 import numpy as np
@@ -49,18 +49,10 @@ def test_fullsize(cfg):
     xsup, supno = oracle.supernodes(m.n, cnt - lcnt, l_rptr, l_ridx, 128)
     assert res.nsuper == len(xsup) - 1
     assert np.array_equal(res.xsup, xsup) and np.array_equal(res.supno, supno)
-    # column counts of L: bincount of the row-wise column ids
-    col_cnt = np.bincount(l_ridx, minlength=m.n)
-    assert np.array_equal(np.diff(res.l_ptr), col_cnt)
-    # sampled L columns through the transpose
-    tp, ti = oracle.csr_to_csc(m.n, m.row_ptr, m.col_idx)
-    rng = np.random.default_rng(cfg)
-    cols = np.unique(np.concatenate([np.arange(m.n - 256, m.n), np.arange(0, 64),
-                                     rng.choice(m.n, 512, replace=False)])).astype(np.int32)
-    c2, l2, e2, p2, ent2 = oracle.rows_struct(m.n, tp.astype(np.int32), ti, cols)
-    for k, c in enumerate(cols):
-        seg = ent2[p2[k]:p2[k + 1]]
-        want = seg[seg > c]
-        got = res.l_idx[res.l_ptr[c]:res.l_ptr[c + 1]]
-        assert np.array_equal(got, want), f"L column {c}"
-    _say("full-size parity ok")
+    # L column-wise, every array in full
+    l_ptr, l_idx = oracle.csr_to_csc(m.n, l_rptr, l_ridx)
+    del l_rptr, l_ridx
+    assert np.array_equal(res.l_ptr, l_ptr), "L column pointers differ"
+    assert np.array_equal(res.l_idx, l_idx), "L row indices differ"
+    assert res.fills == res.nnz_l + res.nnz_u - oracle.pattern_with_diag_nnz(m.n, m.row_ptr, m.col_idx)
+    _say(f"full-size parity ok: {res.nnz_l + res.nnz_u} entries compared")

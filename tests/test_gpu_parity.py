@@ -40,8 +40,7 @@ def assert_same(res, ref, check_sn=True, l_csr=False):
         assert np.array_equal(res.xsup, ref.xsup) and np.array_equal(res.supno, ref.supno)
     assert res.stats["edges_alg"] == ref.edges_alg
     assert res.nnz_l == ref.nnz_l and res.nnz_u == ref.nnz_u
-    fills = ref.nnz_l + ref.nnz_u - oracle.pattern_with_diag_nnz(ref.n, *_csr_of(ref))
-    assert res.fills == fills
+    assert res.fills == oracle.fills(ref, *_csr_of(ref))
 
 
 _CSR = {}
@@ -311,7 +310,9 @@ def test_autotuner_trials_keep_results(g):
     _say(f"tuner on n={m.n}")
     res = g.symbolic(m.n, m.row_ptr, m.col_idx, flags=g.TUNE_NOW)
     assert res.stats["t_tune_ms"] > 0
-    assert res.stats["mapping"] in (0, 2, 3) and 1 <= res.stats["window"] <= 64
+    # the tuner's candidates: 32-bit labels at eight (0) or seven (4) wavefronts
+    # per SIMD, byte states (3)
+    assert res.stats["mapping"] in (0, 3, 4) and 1 <= res.stats["window"] <= 64
     assert_same(res, ref)
     again = g.symbolic(m.n, m.row_ptr, m.col_idx)
     assert again.stats["t_tune_ms"] == 0

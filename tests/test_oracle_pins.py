@@ -6,7 +6,7 @@ import pytest
 import oracle
 import synth
 from oracle import trace
-from conftest import adj_to_csr, parse_adj, read_golden
+from conftest import adj_to_csr, oracle_members, parse_adj, read_golden
 
 
 def _csr_from_dense(D):
@@ -355,3 +355,85 @@ def test_i7_symmetric_pattern_gives_symmetric_fill():
     res = oracle.symbolic(m.n, m.row_ptr, m.col_idx)
     F = oracle.dense_from_symbolic(res)
     assert (F == F.T).all()
+
+
+# ---- test helpers of the oracle: the transpose and the fill count ---------
+
+@pytest.mark.parametrize("seed", range(6))
+def test_transpose_helper_against_dense(seed):
+    """oracle.csr_to_csc against the dense transpose, with columns shuffled
+    inside rows (the helper must still list each column's rows ascending)."""
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(1, 70))
+    D = _random_digraph(n, 0.15, rng, diag=bool(seed % 2))
+    rp, ci = _csr_from_dense(D)
+    ci = ci.copy()
+    for i in range(n):
+        rng.shuffle(ci[rp[i]:rp[i + 1]])
+    tp, ti = oracle.csr_to_csc(n, rp, ci)
+    assert tp[0] == 0 and tp[-1] == D.sum()
+    for c in range(n):
+        assert ti[tp[c]:tp[c + 1]].tolist() == np.nonzero(D[:, c])[0].tolist()
+
+
+def test_transpose_helper_edge_cases():
+    tp, ti = oracle.csr_to_csc(0, np.zeros(1, np.int64), np.zeros(0, np.int32))
+    assert tp.tolist() == [0] and len(ti) == 0
+    # empty rows and columns
+    tp, ti = oracle.csr_to_csc(4, np.array([0, 0, 2, 2, 3]), np.array([3, 0, 3], np.int32))
+    assert tp.tolist() == [0, 1, 1, 1, 3] and ti.tolist() == [1, 1, 3]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_pattern_with_diag_nnz_brute_force(seed):
+    """nnz(pattern(A) union diag) against the dense count, rows with and
+    without a stored diagonal mixed."""
+    rng = np.random.default_rng(600 + seed)
+    n = int(rng.integers(1, 60))
+    D = _random_digraph(n, 0.1, rng, diag=False)
+    D[np.diag_indices(n)] = rng.random(n) < 0.5
+    rp, ci = _csr_from_dense(D)
+    assert oracle.pattern_with_diag_nnz(n, rp, ci) == int((D | np.eye(n, dtype=bool)).sum())
+
+
+def test_fill_count_closed_forms():
+    """fills = nnz(L+U) - nnz(pattern(A) union diag) (dataset table,
+    "#Fill-in") on patterns whose fill is known in closed form."""
+    n = 50
+    tri = np.eye(n, dtype=bool) | np.eye(n, k=1, dtype=bool) | np.eye(n, k=-1, dtype=bool)
+    rp, ci = _csr_from_dense(tri)
+    assert oracle.fills(oracle.symbolic(n, rp, ci), rp, ci) == 0
+    # the same without stored diagonal entries: U still holds the diagonal
+    rp, ci = _csr_from_dense(tri & ~np.eye(n, dtype=bool))
+    assert oracle.pattern_with_diag_nnz(n, rp, ci) == 3 * n - 2
+    assert oracle.fills(oracle.symbolic(n, rp, ci), rp, ci) == 0
+    n = 40
+    arrow = np.eye(n, dtype=bool)
+    arrow[0, :] = True
+    arrow[:, 0] = True
+    rp, ci = _csr_from_dense(arrow)
+    assert oracle.fills(oracle.symbolic(n, rp, ci), rp, ci) == n * n - (3 * n - 2)
+    arrow = np.eye(n, dtype=bool)
+    arrow[-1, :] = True
+    arrow[:, -1] = True
+    rp, ci = _csr_from_dense(arrow)
+    assert oracle.fills(oracle.symbolic(n, rp, ci), rp, ci) == 0
+    # 40x40 5-point stencil, nothing dropped, natural order: the envelope
+    # (126,478 entries) minus the stencil's own couplings, 1,600 diagonal
+    # entries plus 2 * 2 * 40 * 39 neighbour pairs
+    m = synth.stencil(5, (40, 40), nd=False, seed=1, drop_thresh=0)
+    res = oracle.symbolic(m.n, m.row_ptr, m.col_idx)
+    assert oracle.pattern_with_diag_nnz(m.n, m.row_ptr, m.col_idx) == 1600 + 4 * 40 * 39
+    assert oracle.fills(res, m.row_ptr, m.col_idx) == 126478 - 7840
+
+
+def test_oracle_members_helper_matches_single_calls():
+    """The test helper that runs O1 on a block-diagonal concatenation of many
+    matrices gives every matrix's own result."""
+    mats = [synth.batch_member(k) for k in (0, 1, 7, 4095)]
+    for m, a in zip(mats, oracle_members(mats)):
+        b = oracle.symbolic(m.n, m.row_ptr, m.col_idx)
+        assert np.array_equal(a.u_ptr, b.u_ptr) and np.array_equal(a.u_idx, b.u_idx)
+        assert np.array_equal(a.l_ptr, b.l_ptr) and np.array_equal(a.l_idx, b.l_idx)
+        assert np.array_equal(a.xsup, b.xsup) and np.array_equal(a.supno, b.supno)
+        assert a.edges_alg == b.edges_alg
