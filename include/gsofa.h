@@ -287,6 +287,56 @@ GSOFA_API int gsofa_release_cache(void);
  * out[2] graph launches. out must hold 3 entries; GSOFA_EINVAL if NULL. */
 GSOFA_API int gsofa_graph_counters(uint64_t* out);
 
+/*
+ * For callers that cannot allocate device memory (code between the nodes of a
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * gsofa_symbolic on device-resident input into caller-provided device output
+ * arrays, with no device allocation at all. Every working buffer is carved
+ * from one fixed scratch array of GSOFA_NOALLOC_SCRATCH_BYTES that the library
+ * holds in device memory on every GPU it runs on, from the first call on that
+ * GPU until the process ends; it calls no hipMalloc, hipFree or other
+ * allocating routine, and no caller allocator.
+ *   row_ptr[n+1], col_idx[row_ptr[n]]: device pointers, as for
+ *     GSOFA_INPUT_ON_DEVICE (checked on the device; GSOFA_EINVAL if malformed).
+ *   u_ptr[n+1] (int64), u_idx[u_cap]: U in CSR; l_ptr[n+1] (int64),
+ *     l_idx[l_cap]: L in CSC (CSR with GSOFA_L_CSR); xsup[n+1], supno[n]:
+ *     supernodes (may be NULL with GSOFA_NO_SUPERNODES). All device pointers,
+ *     caller-owned; n >= 0 and u_ptr, l_ptr non-NULL even for n = 0.
+ *   counts (host, caller-owned): nnz and fill totals, nsuper, statistics, and
+ *     scratch_bytes, the scratch the call needed (or would have needed).
+ *   opts: stream, window, concurrent_sources, max_supernode and the flags
+ *     GSOFA_NO_SUPERNODES, GSOFA_L_CSR, GSOFA_NO_LINE95, GSOFA_LEVEL_ORDER,
+ *     GSOFA_MAP_WAVE32, GSOFA_MAP_WAVE32_7, GSOFA_INPUT_ON_DEVICE,
+ *     GSOFA_RESULT_ON_DEVICE, GSOFA_EAGER, GSOFA_NO_TUNE; any other flag, a
+ *     caller allocator or a memory budget -> GSOFA_EINVAL.
+ * GSOFA_ECAPACITY (with counts->scratch_bytes and, once known, the nnz totals
+ * set) when the matrix needs more than the scratch array holds -- its per-row
+ * arrays and at least one source's state up front, the output structure after
+ * fill detection -- or when u_cap / l_cap are below nnz(U) / nnz(L); the
+ * output arrays then hold no result (their contents are unspecified).
+ * Otherwise the result equals gsofa_symbolic's.
+ * Calls share the one scratch array of their GPU, which keeps the previous
+ * call's contents (every call clears what it needs cleared): the entry point
+ * holds a process-wide lock and returns only after its device work on
+ * opts->stream has completed, so calls from one process never overlap; calls
+ * that bypassed this (none can through this ABI) would race on it.
+ */
+#define GSOFA_NOALLOC_SCRATCH_BYTES (128ull << 20)
+
+typedef struct {
+    int64_t nnz_a, nnz_l, nnz_u, fills;
+    int32_t nsuper;
+    int32_t pad_;
+    int64_t scratch_bytes;      /* scratch needed by this call (what it would need on
+                                   GSOFA_ECAPACITY)                                       */
+    gsofa_stats stats;
+} gsofa_counts;
+
+GSOFA_API int gsofa_symbolic_noalloc(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                                     const gsofa_opts* opts, int64_t* u_ptr, int32_t* u_idx,
+                                     int64_t u_cap, int64_t* l_ptr, int32_t* l_idx, int64_t l_cap,
+                                     int32_t* xsup, int32_t* supno, gsofa_counts* counts);
+
 /* Process-wide device-memory counters since load, for the current device and
  * all others together: out[0] bytes the library currently holds from its own
  * hipMalloc calls (in use and cached idle), out[1] hipMalloc calls made by the

@@ -39,7 +39,9 @@ RESET_LABELS = 0x10000
 
 EXPORTED = ["gsofa_symbolic", "gsofa_batch", "gsofa_serve_open", "gsofa_serve_submit",
             "gsofa_serve_poll", "gsofa_serve_close", "gsofa_result_free", "gsofa_strerror",
-            "gsofa_release_cache", "gsofa_graph_counters", "gsofa_memory_counters"]
+            "gsofa_release_cache", "gsofa_graph_counters", "gsofa_memory_counters",
+            "gsofa_symbolic_noalloc"]
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 class GsofaError(RuntimeError):
@@ -75,6 +77,12 @@ class Opts(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN),
                 ("dev_free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
                 ("queue_cap", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class Counts(ctypes.Structure):
+    _fields_ = [("nnz_a", ctypes.c_int64), ("nnz_l", ctypes.c_int64), ("nnz_u", ctypes.c_int64),
+                ("fills", ctypes.c_int64), ("nsuper", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("scratch_bytes", ctypes.c_int64), ("stats", Stats)]
 
 
 class Result(ctypes.Structure):
@@ -120,6 +128,12 @@ def load():
         lib.gsofa_release_cache.argtypes = []
         lib.gsofa_graph_counters.restype = ctypes.c_int
         lib.gsofa_graph_counters.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
+        lib.gsofa_symbolic_noalloc.restype = ctypes.c_int
+        lib.gsofa_symbolic_noalloc.argtypes = [
+            ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, P(Opts),
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+            ctypes.c_void_p, ctypes.c_void_p, P(Counts)]
         lib.gsofa_memory_counters.restype = ctypes.c_int
         lib.gsofa_memory_counters.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
         _lib = lib
@@ -383,6 +397,45 @@ def batch(mats, flags=0, max_supernode=0, mem_budget_bytes=0, window=0,
                 r.free()
         raise GsofaError(rc, "gsofa_batch")
     return results
+
+
+def _dptr(t):
+    """Device pointer of a contiguous torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("no-allocation arrays must be contiguous device tensors")
+    return t.data_ptr()
+
+
+def symbolic_noalloc(n, row_ptr, col_idx, u_ptr, u_idx, l_ptr, l_idx, xsup=None, supno=None,
+                     flags=0, max_supernode=0, window=0, concurrent_sources=0, stream=None):
+    """gsofa_symbolic_noalloc: device int32 CSR in, results written into the
+    caller's device tensors (u_ptr/l_ptr int64 [n+1], u_idx/l_idx int32 with
+    their lengths as capacities, xsup int32 [n+1], supno int32 [n]); no device
+    allocation. Returns the counts as a dict; raises GsofaError (with
+    ``.counts`` set on ECAPACITY)."""
+    import torch
+    for name, t, dt in (("row_ptr", row_ptr, torch.int32), ("col_idx", col_idx, torch.int32),
+                        ("u_ptr", u_ptr, torch.int64), ("l_ptr", l_ptr, torch.int64),
+                        ("u_idx", u_idx, torch.int32), ("l_idx", l_idx, torch.int32),
+                        ("xsup", xsup, torch.int32), ("supno", supno, torch.int32)):
+        if t is not None and t.dtype != dt:
+            raise TypeError(f"{name} must be {dt}")
+    o = make_opts(flags | INPUT_ON_DEVICE, max_supernode, 0, window, concurrent_sources, stream)
+    c = Counts()
+    rc = load().gsofa_symbolic_noalloc(
+        int(n), _dptr(row_ptr), _dptr(col_idx), ctypes.byref(o),
+        _dptr(u_ptr), _dptr(u_idx), int(u_idx.numel()),
+        _dptr(l_ptr), _dptr(l_idx), int(l_idx.numel()),
+        _dptr(xsup), _dptr(supno), ctypes.byref(c))
+    out = {f: getattr(c, f) for f, _ in Counts._fields_ if f not in ("stats", "pad_")}
+    out["stats"] = {f: getattr(c.stats, f) for f, _ in Stats._fields_}
+    if rc != OK:
+        err = GsofaError(rc, "gsofa_symbolic_noalloc")
+        err.counts = out if rc == ECAPACITY else None
+        raise err
+    return out
 
 
 class Server:

@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgsofa.so")
-SOURCES = ["gsofa_kernels.hip", "gsofa_host.hip"]
+SOURCES = ["gsofa_kernels.hip", "gsofa_host.hip", "gsofa_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
