@@ -650,6 +650,9 @@ struct MatIn {
 
 // Calls with fewer sources are latency-bound and use the defaults untuned.
 constexpr int64_t kTuneMinSources = 65536;
+// Memory-budget mode: pinned host memory for worklist and row-buffer overflow,
+// at most this much per band (it bounds the sources in flight as well).
+constexpr int64_t kSpillHostBytes = int64_t(32) << 30;
 
 struct Plan {
     int32_t window;
@@ -657,6 +660,7 @@ struct Plan {
     int32_t max_super;  // <= 0: unbounded
     uint32_t flags;
     int64_t budget;
+    int32_t queue_cap;  // memory-budget mode: device entries per worklist and row buffer
     bool window_auto;   // window span, mapping and sources in flight are the tuner's
     bool allow_trials;  // the tuner may time trial launches in this call
 };
@@ -671,6 +675,8 @@ struct Plan {
 // already in the structure, so the paper's order (window = n) and the
 // line-9.5-off ablation always run on 32-bit labels.
 int choose_mapping(uint32_t flags, int32_t window) {
+    if (flags & GSOFA_BUDGET_MODE) return 5;
+    if (flags & GSOFA_MAP_THREAD) return 6;
     if (flags & GSOFA_MAP_WG16) return 1;
     if (flags & GSOFA_MAP_WG8) return 2;
     if (flags & GSOFA_MAP_WAVE32) return 0;
@@ -916,8 +922,12 @@ struct Engine {
         // default budget: free device memory plus what this library holds idle
         int64_t budget = plan.budget > 0 ? plan.budget : (int64_t)((di.free_b + di.reclaimable) * 0.9);
         const int64_t fixed = fixed_bytes(nrows, total_nnz);
-        if (budget < fixed + lay.bytes_per_slot) throw Status{GSOFA_ENOMEM};
-        const int64_t slot_fit = std::max<int64_t>((budget - fixed) / 2 / lay.bytes_per_slot, 1);
+        // memory-budget mode: the budget caps the source-slot state alone (the
+        // paper's shared arena of frontier queues, labels and stamps); inputs,
+        // per-row arrays and the output are outside it
+        const bool budget_mode = (plan.flags & GSOFA_BUDGET_MODE) != 0;
+        if (!budget_mode && budget < fixed + lay.bytes_per_slot) throw Status{GSOFA_ENOMEM};
+        const int64_t slot_fit = budget_mode ? 1 : std::max<int64_t>((budget - fixed) / 2 / lay.bytes_per_slot, 1);
         // sources in flight for a mapping: the resident wavefronts (or blocks),
         // within half of the memory left after the fixed part
         auto plan_slots = [&](int map) {
@@ -926,7 +936,7 @@ struct Engine {
             // slots (8,192), the 1000^2 stencil (4 MB per source) gained nothing
             // beyond 4,096
             int64_t want = plan.nslots > 0 ? plan.nslots : (int64_t)traverse_resident_slots(di.cus, map);
-            if (plan.nslots <= 0 && (map == 0 || map == 3 || map == 4))
+            if (plan.nslots <= 0 && (map == 0 || map == 3 || map == 4 || map == 6))
                 want = std::min<int64_t>(want, std::max<int64_t>(1024, (int64_t(16) << 30) / (4 * N)));
             want = std::min<int64_t>(want, std::max<int64_t>(items, 1));
             int64_t ns = std::max<int64_t>(std::min<int64_t>(want, slot_fit), 1);
@@ -962,14 +972,19 @@ struct Engine {
                 tune_table()[key] = c;
             }
         }
-        const int64_t nslots = plan_slots(mapping);
+        const int64_t nslots = budget_mode ? 0 : plan_slots(mapping);
 
         int64_t pool_cap = pool_estimate(nrows, total_nnz);
-        const int64_t pool_room = (budget - fixed - nslots * lay.bytes_per_slot) / 4 / 3;
-        pool_cap = std::max<int64_t>(std::min<int64_t>(pool_cap, pool_room), nrows + 1024);
+        if (!budget_mode) {
+            const int64_t pool_room = (budget - fixed - nslots * lay.bytes_per_slot) / 4 / 3;
+            pool_cap = std::max<int64_t>(std::min<int64_t>(pool_cap, pool_room), nrows + 1024);
+        }
 
-        auto slots = take_slots(lay, (int32_t)nslots, mapping == 3 ? 1 : 0, st);
-        const bool graphs = (plan.flags & GSOFA_EAGER) == 0;
+        // slot modes: 0 32-bit labels, 1 byte states, 2 visit stamps of the
+        // one-thread-per-source kernel (a different mode re-initialises a set)
+        std::unique_ptr<SlotSet> slots;
+        if (!budget_mode) slots = take_slots(lay, (int32_t)nslots, mapping == 3 ? 1 : mapping == 6 ? 2 : 0, st);
+        const bool graphs = (plan.flags & GSOFA_EAGER) == 0 && !budget_mode;
 
         DBuf row_off(8 * (size_t)std::max<int64_t>(nrows, 1));
         DBuf row_cnt(4 * (size_t)std::max<int64_t>(nrows, 1));
@@ -995,15 +1010,17 @@ struct Engine {
         TraverseArgs ta{};
         ta.jobs = d_jobs.as<Job>();
         ta.njobs = nj;
-        ta.nslots = slots->nslots < nslots ? slots->nslots : (int32_t)nslots;
+        if (slots) {
+            ta.nslots = slots->nslots < nslots ? slots->nslots : (int32_t)nslots;
+            ta.slots = slots->buf.as<uint8_t>();
+            ta.lay = slots->lay;
+        }
         ta.nitems = items;
         ta.item_rows = nullptr;
         ta.row_job = d_row_job.as<int32_t>();
         ta.item_job = d_item_job.as<int32_t>();
         ta.row_stats = row_stats.as<RowStat>();
         ta.item_counter = counters.as<unsigned long long>();
-        ta.slots = slots->buf.as<uint8_t>();
-        ta.lay = slots->lay;
         ta.row_off = row_off.as<int64_t>();
         ta.row_cnt = row_cnt.as<int32_t>();
         ta.row_lcnt = row_lcnt.as<int32_t>();
@@ -1014,8 +1031,94 @@ struct Engine {
         ta.window = plan.window;
         ta.flags = plan.flags;
         ta.mapping = mapping;
+
+        // Memory-budget mode (Space Optimization section). Sources run in bands
+        // of decreasing ids, each band one launch whose slots hold labels, level
+        // stamps and the pending bitmap for the ids below the band's largest
+        // source only (bubble removal), so a band of smaller ids fits more
+        // sources into the same budget (dynamic space allocation); the budget
+        // gets as many slots as fit, at most the resident wavefronts, and a band
+        // reaching that many takes all remaining sources. Worklists and row
+        // buffers keep queue_cap entries on the device and spill the rest to
+        // pinned host memory (external frontier management).
+        int32_t band_launches = 0;
+        int32_t budget_max_c = 0;
+        int64_t budget_peak_slots = 0;
+        const int64_t slot_budget =
+            plan.budget > 0 ? plan.budget
+                            : std::max<int64_t>((int64_t)((di.free_b + di.reclaimable) * 0.9) - fixed - 4 * pool_cap,
+                                                int64_t(64) << 20);
+        auto run_budget = [&](const std::vector<int32_t>& rows, const std::vector<int32_t>& local) {
+            // rows: global rows; local: their ids inside their matrix; both in
+            // order of decreasing local id
+            if (rows.empty()) return;
+            const int64_t R5 = traverse_resident_slots(di.cus, 5);
+            DBuf d_rows(4 * rows.size());
+            chk(hipMemcpyAsync(d_rows.p, rows.data(), 4 * rows.size(), hipMemcpyHostToDevice, st));
+            size_t pos = 0;
+            int64_t hi = (int64_t)local[0] + 1;
+            while (pos < rows.size()) {
+                const SlotLayout lb = slot_layout_budget(N, hi, plan.queue_cap > 0 ? plan.queue_cap : 8192);
+                int64_t C = std::min<int64_t>(R5, slot_budget / lb.bytes_per_slot);
+                C = std::min<int64_t>(C, kSpillHostBytes / std::max<int64_t>(4 * lb.h_stride, 1));
+                if (plan.nslots > 0) C = std::min<int64_t>(C, plan.nslots);
+                if (C < 1) throw Status{GSOFA_ENOMEM};
+                const int64_t lo = (C >= R5 || hi <= 4096) ? 0 : hi / 2;
+                size_t end = pos;
+                while (end < rows.size() && local[end] >= lo) ++end;
+                int64_t ns = std::min<int64_t>(C, (int64_t)(end - pos));
+                if (ns > 4) ns = ns / 4 * 4;
+                DBuf sl((size_t)ns * (size_t)lb.bytes_per_slot);
+                chk(launch_init_slots(sl.as<uint8_t>(), (int32_t)ns, lb, st));
+                PinnedBuf spill((size_t)std::max<int64_t>(ns * lb.h_stride, 1) * 4);
+                TraverseArgs tb = ta;
+                tb.slots = sl.as<uint8_t>();
+                tb.lay = lb;
+                tb.nslots = (int32_t)ns;
+                tb.item_rows = d_rows.as<int32_t>() + pos;
+                tb.nitems = (int64_t)(end - pos);
+                tb.item_job = nullptr;
+                tb.row_job = nj > 1 ? d_row_job.as<int32_t>() : nullptr;
+                tb.host_spill = spill.as<int32_t>();
+                tb.mapping = 5;
+                chk(launch_zero_i32(counters.as<int32_t>(), 2, st));  // the item counter only
+                chk(launch_traverse(tb, st));
+                ++band_launches;
+                budget_max_c = std::max<int32_t>(budget_max_c, (int32_t)ns);
+                budget_peak_slots = std::max<int64_t>(budget_peak_slots, ns * lb.bytes_per_slot);
+                // the band's slots and spill area are released next
+                chk(hipStreamSynchronize(st));
+                pos = end;
+                hi = lo;
+            }
+        };
+        // local id of a global row (matrices in the user's order, row_base increasing)
+        auto local_of = [&](int32_t r) -> int32_t {
+            const auto it = std::upper_bound(row_base.begin(), row_base.end(), (int64_t)r);
+            return (int32_t)(r - *(it - 1));
+        };
+
         chk(hipEventRecord(ev[0], st));
-        {
+        if (budget_mode) {
+            if (nj > 1) chk(launch_row_job(d_jobs.as<Job>(), nj, N, d_row_job.as<int32_t>(), st));
+            chk(launch_zero_i32(counters.as<int32_t>(), 16, st));
+            chk(launch_zero_i32(jst.as<int32_t>(), (int64_t)(sizeof(JobStats) / 4) * nj, st));
+            // every source, largest ids first (the job table is sorted by size)
+            std::vector<int32_t> rows, local;
+            rows.reserve((size_t)items);
+            local.reserve((size_t)items);
+            for (int64_t sid = N - 1; sid >= 0; --sid)
+                for (int32_t q = 0; q < nj && jt[q].n > sid; ++q) {
+                    rows.push_back((int32_t)(jt[q].row_base + sid));
+                    local.push_back((int32_t)sid);
+                }
+            run_budget(rows, local);
+            chk(launch_job_stats(d_jobs.as<Job>(), nj, N, row_stats.as<RowStat>(), jst.as<JobStats>(), st));
+            chk(hipMemcpyAsync(hst, jst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, st));
+            chk(hipMemcpyAsync(h_tail, counters.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, st));
+            chk(hipEventRecord(ev[4], st));
+            chk(hipStreamSynchronize(st));
+        } else {
             // phase 1: one persistent traversal launch over every source of every matrix
             Phase ph(kPhaseTraverse, graphs, st);
             const hipStream_t s = ph.stream();
@@ -1037,7 +1140,7 @@ struct Engine {
 
         bool overflow = false;
         float t_trav_extra = 0;
-        int32_t n_launches = 1;
+        int32_t n_launches = budget_mode ? band_launches : 1;
         for (int32_t q = 0; q < nj; ++q) {
             if (hst[q].err & kErrDuplicate) jstat[ord[q]] = GSOFA_EINVAL;
             if (hst[q].err & kErrOverflow) overflow = true;
@@ -1074,8 +1177,24 @@ struct Engine {
             chk(hipEventElapsedTime(&first_ms, ev[0], ev[4]));
             t_trav_extra += first_ms;
             chk(hipEventRecord(ev[0], st));
-            chk(launch_traverse(ta, st));
-            ++n_launches;
+            if (budget_mode) {
+                std::vector<int32_t> loc(redo.size());
+                for (size_t i = 0; i < redo.size(); ++i) loc[i] = local_of(redo[i]);
+                std::vector<size_t> perm(redo.size());
+                for (size_t i = 0; i < perm.size(); ++i) perm[i] = i;
+                std::stable_sort(perm.begin(), perm.end(), [&](size_t x, size_t y) { return loc[x] > loc[y]; });
+                std::vector<int32_t> rr(redo.size()), ll(redo.size());
+                for (size_t i = 0; i < perm.size(); ++i) {
+                    rr[i] = redo[perm[i]];
+                    ll[i] = loc[perm[i]];
+                }
+                const int32_t before = band_launches;
+                run_budget(rr, ll);
+                n_launches += band_launches - before;
+            } else {
+                chk(launch_traverse(ta, st));
+                ++n_launches;
+            }
             chk(hipEventRecord(ev[4], st));
             chk(launch_job_stats(d_jobs.as<Job>(), nj, N, row_stats.as<RowStat>(), jst.as<JobStats>(), st));
             chk(hipMemcpyAsync(hst, jst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, st));
@@ -1088,7 +1207,7 @@ struct Engine {
             pool_cap = new_cap;
         }
         chk(hipEventRecord(ev[1], st));
-        give_slots(std::move(slots));
+        if (slots) give_slots(std::move(slots));
         if (total_nnz > 0)
             g_fill_ratio.store(std::max(4.0, (double)*h_tail / (double)total_nnz));
 
@@ -1328,9 +1447,10 @@ struct Engine {
             r->stats.edges_gpu = hst[q].edges_gpu;
             r->stats.iterations = hst[q].iterations;
             r->stats.windows = hst[q].windows;
-            r->stats.concurrent_sources = ta.nslots;
+            r->stats.concurrent_sources = budget_mode ? budget_max_c : ta.nslots;
             r->stats.peak_device_bytes =
-                (uint64_t)(nslots * lay.bytes_per_slot + pool_cap * 4 + nrows * 48 + (nnz_u + 3 * nnz_l) * 4);
+                (uint64_t)((budget_mode ? budget_peak_slots : nslots * lay.bytes_per_slot) + pool_cap * 4 + nrows * 48 +
+                           (nnz_u + 3 * nnz_l) * 4);
             r->stats.t_traverse_ms = t_trav;
             r->stats.t_emit_ms = t_emit;
             r->stats.t_supernode_ms = t_sn;
@@ -1338,7 +1458,7 @@ struct Engine {
             r->stats.mapping = mapping;
             r->stats.t_tune_ms = t_tune;
             r->stats.launches = n_launches;
-            r->stats.spilled_entries = 0;
+            r->stats.spilled_entries = hst[q].spilled;
             if (jstat[j] != GSOFA_OK) continue;
             const int64_t n = mats[j].n, b = row_base[j];
             r->nnz_a = nnz[j];
@@ -1516,6 +1636,7 @@ Plan make_plan(const gsofa_opts* o) {
     p.budget = 0;
     p.window_auto = false;
     p.allow_trials = true;
+    p.queue_cap = 0;
     if (o) {
         p.flags = o->flags;
         p.budget = o->mem_budget_bytes;
@@ -1523,6 +1644,7 @@ Plan make_plan(const gsofa_opts* o) {
         if (o->max_supernode > 0) p.max_super = o->max_supernode;
         else if (o->max_supernode < 0) p.max_super = 0;
         p.window = o->window;
+        p.queue_cap = o->queue_cap;
     }
     return p;
 }
@@ -1553,7 +1675,8 @@ int run_engine(std::vector<MatIn> mats, const gsofa_opts* o, std::vector<gsofa_r
     }
     eng.plan.window_auto = eng.plan.window <= 0 && eng.plan.nslots <= 0 &&
                            (eng.plan.flags & (GSOFA_MAP_WAVE32 | GSOFA_MAP_WAVE32_7 | GSOFA_MAP_WG8 | GSOFA_MAP_WG16 | GSOFA_MAP_BYTE |
-                                              GSOFA_LEVEL_ORDER | GSOFA_NO_LINE95)) == 0;
+                                              GSOFA_LEVEL_ORDER | GSOFA_NO_LINE95 | GSOFA_BUDGET_MODE | GSOFA_MAP_THREAD |
+                                              GSOFA_RESET_LABELS)) == 0;
     if (eng.plan.window <= 0) eng.plan.window = auto_window(rows);
     if (eng.plan.flags & GSOFA_LEVEL_ORDER) eng.plan.window = (int32_t)std::min<int64_t>(N, 0x7FFFFFFF);
     // a caller allocator serves every device buffer of this call; buffers it

@@ -27,6 +27,7 @@ struct JobStats {
     unsigned long long iterations;
     unsigned long long windows;
     unsigned long long diag;  // rows with a stored diagonal entry
+    unsigned long long spilled;  // worklist / row-buffer entries written to host memory
     int32_t err;              // bit 0: repeated column in a row; bit 1: pool overflow
     int32_t pad;
 };
@@ -44,15 +45,27 @@ constexpr int32_t kErrDuplicate = 1;
 constexpr int32_t kErrOverflow = 2;
 
 // Working state of one source slot (one wavefront). N = largest n of the launch.
+// Labels, level stamps and the pending bitmap cover ids below L (L = N, or in
+// memory-budget mode the largest source id of the band plus one: no vertex at
+// or above the source is ever labelled). Worklists and the row buffer hold
+// qcap_d / rcap_d entries in device memory; in memory-budget mode the rest of
+// their worst case (h_q entries per worklist, N - rcap_d for the row buffer)
+// lies in pinned host memory, h_stride entries per slot.
 struct SlotLayout {
     int64_t N;
+    int64_t L;
     int64_t nw64;             // 64-bit words of the pending bitmap
-    int64_t qcap;             // worklist capacity
-    int64_t off_lab, off_p, off_qs, off_qa, off_qb, off_row, off_touch, off_meta;
+    int64_t qcap;             // worklist capacity (device and host parts together)
+    int64_t qcap_d, rcap_d;   // device entries per worklist / row buffer
+    int64_t h_q, h_stride;    // host entries per worklist / per slot (budget mode)
+    int64_t off_lab, off_p, off_qs, off_qa, off_qb, off_row, off_touch, off_meta, off_ub;
     int64_t bytes_per_slot;
 };
 
 SlotLayout slot_layout(int64_t N);
+// Memory-budget layout: labels for ids below L, a U-membership bitmap over N
+// ids, qcap_d device entries per worklist and row buffer.
+SlotLayout slot_layout_budget(int64_t N, int64_t L, int64_t qcap_d);
 
 struct TraverseArgs {
     const Job* jobs;
@@ -77,7 +90,9 @@ struct TraverseArgs {
     uint32_t flags;
     int32_t mapping;                  // 0: one wavefront per source (32-bit labels); 1: 16, 2: 8
                                       // wavefronts per source; 3: one wavefront, byte states;
-                                      // 4: as 0, compiled for seven wavefronts per SIMD
+                                      // 4: as 0, compiled for seven wavefronts per SIMD;
+                                      // 5: memory-budget kernel; 6: one thread per source (fill2)
+    int32_t* host_spill;              // budget mode: pinned host memory, lay.h_stride entries per slot
 };
 
 // Row-space description shared by the assembly kernels. With one job,

@@ -134,11 +134,15 @@ SlotLayout slot_layout(int64_t N) {
         o += (bytes + 255) & ~int64_t(255);
         return r;
     };
+    L.L = N;
     L.qcap = N + 2048;
+    L.qcap_d = L.qcap;
+    L.rcap_d = N;
     L.off_lab = take(4 * N);
     L.off_p = take(8 * L.nw64);
     L.off_qs = take(4 * N);
     L.off_meta = take(64);
+    L.off_ub = 0;
     L.off_qa = take(4 * L.qcap);
     L.off_qb = take(4 * L.qcap);
     L.off_row = take(4 * N);
@@ -147,11 +151,45 @@ SlotLayout slot_layout(int64_t N) {
     return L;
 }
 
+SlotLayout slot_layout_budget(int64_t N, int64_t Lb, int64_t qcap_d) {
+    SlotLayout L{};
+    if (N < 1) N = 1;
+    if (Lb < 1) Lb = 1;
+    if (Lb > N) Lb = N;
+    L.N = N;
+    L.L = Lb;
+    L.nw64 = (Lb + 63) / 64;
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t r = o;
+        o += (bytes + 255) & ~int64_t(255);
+        return r;
+    };
+    // a worklist never holds more than the ids below L plus the level filter's
+    // slack; the row buffer at most N entries
+    L.qcap = Lb + 2048;
+    L.qcap_d = std::max<int64_t>(std::min<int64_t>(qcap_d, L.qcap), 64);
+    L.rcap_d = std::max<int64_t>(std::min<int64_t>(qcap_d, N), 64);
+    L.off_lab = take(4 * Lb);
+    L.off_p = take(8 * L.nw64);
+    L.off_qs = take(4 * Lb);
+    L.off_meta = take(64);
+    L.off_ub = take(4 * ((N + 31) / 32));  // cleared with P, qs and meta (before off_qa)
+    L.off_qa = take(4 * L.qcap_d);
+    L.off_qb = take(4 * L.qcap_d);
+    L.off_row = take(4 * L.rcap_d);
+    L.off_touch = 0;
+    L.bytes_per_slot = o;
+    L.h_q = L.qcap - L.qcap_d;
+    L.h_stride = 2 * L.h_q + (N - L.rcap_d);
+    return L;
+}
+
 // ------------------------------------------------------------ slot init
 
 // lab = all ones, P = qs = meta = 0 (everything before off_qa).
 __global__ void k_init_slots(uint8_t* slots, int32_t nslots, SlotLayout lay) {
-    const int64_t words_lab = lay.N;
+    const int64_t words_lab = lay.L;
     const int64_t words_rest = (lay.off_qa - lay.off_p) / 4;
     for (int64_t sl = blockIdx.y; sl < nslots; sl += gridDim.y) {
         uint32_t* base = (uint32_t*)(slots + sl * lay.bytes_per_slot);
@@ -167,7 +205,7 @@ __global__ void k_init_slots(uint8_t* slots, int32_t nslots, SlotLayout lay) {
 
 hipError_t launch_init_slots(uint8_t* slots, int32_t nslots, SlotLayout lay, hipStream_t st) {
     if (nslots <= 0) return hipSuccess;
-    int64_t words = lay.N + (lay.off_qa - lay.off_p) / 4;
+    int64_t words = lay.L + (lay.off_qa - lay.off_p) / 4;
     int gx = (int)std::min<int64_t>((words + 255) / 256, 64);
     int gy = std::min(nslots, 4096);
     hipLaunchKernelGGL(k_init_slots, dim3(gx, gy), dim3(256), 0, st, slots, nslots, lay);
@@ -274,7 +312,15 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t label_rsrc(uint32_t* lab, int6
 // 64^3 27-point stencil seven and six were 4 % and 7 % slower. W = 7 (mapping 4)
 // spills less per source, which pays where sources are many and short: ~4 % on
 // the 1000^2 9-point stencil. The tuner picks between them.
-template <int W>
+//
+// B selects the memory-budget variant (mapping 5, GSOFA_BUDGET_MODE; Space
+// Optimization section): labels, level stamps and the pending bitmap cover the
+// ids below lay.L only (bubble removal: the host runs sources in bands of ids
+// below L), U membership is a bitmap over all ids (a vertex above the source is
+// never labelled), and the worklists and the row buffer keep lay.qcap_d /
+// lay.rcap_d entries in device memory and the rest in pinned host memory
+// (external frontier management). With B false every budget branch folds away.
+template <int W, bool B>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) void k_traverse(TraverseArgs a) {
     __shared__ DealTile tiles[kTravWaves];
     __shared__ unsigned long long pushed[kTravWaves][1 << kHashBits];
@@ -295,9 +341,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     GLOBAL int32_t* rowb = gbl((int32_t*)(sb + a.lay.off_row));
     GLOBAL uint32_t* qs = gbl((uint32_t*)(sb + a.lay.off_qs));
     GLOBAL uint32_t* meta = gbl((uint32_t*)(sb + a.lay.off_meta));
-    const __amdgpu_buffer_rsrc_t lab_r = label_rsrc((uint32_t*)(sb + a.lay.off_lab), a.lay.N);
+    const __amdgpu_buffer_rsrc_t lab_r = label_rsrc((uint32_t*)(sb + a.lay.off_lab), a.lay.L);
+    // budget mode: U membership bits, host parts of the worklists and row buffer
+    GLOBAL uint32_t* ub = gbl((uint32_t*)(sb + a.lay.off_ub));
+    const int32_t qcd = (int32_t)a.lay.qcap_d;
+    const int32_t rcd = (int32_t)a.lay.rcap_d;
+    GLOBAL int32_t* hb = B ? gbl(a.host_spill + (int64_t)slot * a.lay.h_stride) : nullptr;
+    GLOBAL int32_t* qa_h = hb;
+    GLOBAL int32_t* qb_h = B ? hb + a.lay.h_q : nullptr;
+    GLOBAL int32_t* rowb_h = B ? hb + 2 * a.lay.h_q : nullptr;
+    auto qput = [&](GLOBAL int32_t* d, GLOBAL int32_t* h, int32_t i, int32_t v) {
+        if (!B || i < qcd) d[i] = v;
+        else h[i - qcd] = v;
+    };
+    auto qget = [&](GLOBAL int32_t* d, GLOBAL int32_t* h, int32_t i) -> int32_t {
+        return (!B || i < qcd) ? ld_coherent(&d[i]) : ld_coherent(&h[i - qcd]);
+    };
+    auto rput = [&](int32_t i, int32_t v) {
+        if (!B || i < rcd) rowb[i] = v;
+        else rowb_h[i - rcd] = v;
+    };
+    auto rget = [&](int32_t i) -> int32_t {
+        return (!B || i < rcd) ? ld_coherent(&rowb[i]) : ld_coherent(&rowb_h[i - rcd]);
+    };
 
-    const uint32_t R = (uint32_t)a.lay.N;
+    const uint32_t R = (uint32_t)a.lay.L;
     const uint32_t emax = 0xFFFFFFFFu / R;
     uint32_t epoch = meta[0];
     uint32_t lvl = meta[1];
@@ -336,8 +404,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         const GLOBAL int32_t* ci = gbl(a.jobs[j].col_idx);
         const int64_t grow = a.jobs[j].row_base + s;
 
-        // fresh label range for this source (reset once the 32-bit range is used up)
-        if (epoch >= emax) {
+        // fresh label range for this source (reset once the 32-bit range is used
+        // up, or before every source for the ablation of that scheme)
+        if (epoch >= emax || (a.flags & GSOFA_RESET_LABELS)) {
             for (int64_t i = ln; i < (int64_t)R; i += 64) lab[i] = kInf;
             epoch = 0;
             slot_fence();
@@ -359,6 +428,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         unsigned long long e_gpu = 0;
         int32_t rcount = 0, lcount = 0;
         uint32_t n_iter = 0, n_win = 0;
+        unsigned long long n_spill = 0;
 
         // ---- seed: the source row's own entries (original entries of row s)
         const int32_t rs = rp[s], re = rp[s + 1];
@@ -372,14 +442,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
             ndiag += __popcll(__ballot(act && w == s));
             bool fresh = false;
             if (act && w != s) {
-                const uint32_t old = wg_min(&lab[w], base);  // label 0: no intermediate vertex
-                fresh = dec(old) != 0u;
+                if (B && w > s) {
+                    const uint32_t bit = 1u << (w & 31);
+                    fresh = (wg_or(&ub[w >> 5], bit) & bit) == 0u;
+                } else {
+                    const uint32_t old = wg_min(&lab[w], base);  // label 0: no intermediate vertex
+                    fresh = dec(old) != 0u;
+                }
                 dup |= !fresh;
             }
             const bool below = fresh && w < s;
             {
                 unsigned long long m = __ballot(fresh);
-                if (fresh) rowb[rcount + (int32_t)lanes_below(m)] = w;
+                if (fresh) rput(rcount + (int32_t)lanes_below(m), w);
                 rcount += __popcll(m);
             }
             lcount += __popcll(__ballot(below));
@@ -422,6 +497,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
             // extract the pending vertices of [lo, hi) into the worklist
             GLOBAL int32_t* cur = qa;
             GLOBAL int32_t* nxt = qb;
+            GLOBAL int32_t* cur_h = qa_h;
+            GLOBAL int32_t* nxt_h = qb_h;
             int32_t qn = 0;
             const int32_t wlast = (hi - 1) >> 6;
             for (int32_t w0 = lo >> 6; w0 <= wlast; w0 += 64) {
@@ -442,10 +519,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
                 while (word) {
                     const int b = __builtin_ctzll(word);
                     word &= word - 1ull;
-                    cur[o++] = wi * 64 + b;
+                    qput(cur, cur_h, o++, wi * 64 + b);
                 }
                 qn += uni(__shfl(incl, 63, 64));
             }
+            if (B && qn > qcd) n_spill += (unsigned long long)(qn - qcd);
             wave_fence();
 
             // breadth-first label correction inside the window
@@ -461,7 +539,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
                     const int32_t i = c0 + ln;
                     const bool act = i < qn;
                     // bit 31 of a queue entry: first visit of the vertex by this source
-                    const int32_t fr = ld_coherent(&cur[act ? i : 0]);
+                    const int32_t fr = qget(cur, cur_h, act ? i : 0);
                     const int32_t f = fr & 0x7FFFFFFF;
                     const int32_t fs = rp[f];
                     const int32_t deg = act ? rp[f + 1] - fs : 0;
@@ -495,8 +573,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
                         uint32_t lv[kIlp];
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
-                            const uint32_t off = act_e[kk] ? (uint32_t)w[kk] * 4u : 0xFFFFFFF0u;
-                            lv[kk] = __builtin_amdgcn_raw_buffer_load_b32(lab_r, off, 0, 0);
+                            if (B && w[kk] > s) {
+                                lv[kk] = act_e[kk] ? ld_coherent(&ub[w[kk] >> 5]) : ~0u;
+                            } else {
+                                const uint32_t off = act_e[kk] ? (uint32_t)w[kk] * 4u : 0xFFFFFFF0u;
+                                lv[kk] = __builtin_amdgcn_raw_buffer_load_b32(lab_r, off, 0, 0);
+                            }
                         }
                         {
                             const uint32_t dr = dec(fraw);
@@ -516,7 +598,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
                             const uint32_t d = dec(lv[kk]);
-                            if (w[kk] > s) cand[kk] = act_e[kk] && d == kInf;
+                            if (B && w[kk] > s) cand[kk] = act_e[kk] && (lv[kk] & (1u << (w[kk] & 31))) == 0u;
+                            else if (w[kk] > s) cand[kk] = act_e[kk] && d == kInf;
                             else cand[kk] = act_e[kk] && outv[kk] < d && !(line95 && d < (uint32_t)w[kk]);
                         }
                         // Candidates of one round that share a target all saw the label
@@ -554,8 +637,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
                         }
                         uint32_t old[kIlp];
 #pragma unroll
-                        for (int kk = 0; kk < kIlp; ++kk)
-                            old[kk] = cand[kk] ? wg_min(&lab[w[kk]], base + (w[kk] > s ? 0u : outv[kk])) : base;
+                        for (int kk = 0; kk < kIlp; ++kk) {
+                            if (B && w[kk] > s)
+                                // a set bit reads as "already in U", a clear one as "not reached"
+                                old[kk] = cand[kk] ? ((wg_or(&ub[w[kk] >> 5], 1u << (w[kk] & 31)) >> (w[kk] & 31)) & 1u
+                                                          ? base : kInf)
+                                                   : base;
+                            else
+                                old[kk] = cand[kk] ? wg_min(&lab[w[kk]], base + (w[kk] > s ? 0u : outv[kk])) : base;
+                        }
                         bool emit[kIlp], isl[kIlp], push[kIlp], first[kIlp];
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
@@ -614,13 +704,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
                             unsigned long long m = __ballot(emit[kk]);
-                            if (emit[kk]) rowb[rcount + (int32_t)lanes_below(m)] = w[kk];
+                            if (emit[kk]) rput(rcount + (int32_t)lanes_below(m), w[kk]);
                             rcount += __popcll(m);
                             lcount += __popcll(__ballot(isl[kk]));
                             m = __ballot(push[kk]);
                             if (push[kk])
-                                nxt[nq + (int32_t)lanes_below(m)] =
-                                    (int32_t)((uint32_t)w[kk] | (first[kk] ? 0x80000000u : 0u));
+                                qput(nxt, nxt_h, nq + (int32_t)lanes_below(m),
+                                     (int32_t)((uint32_t)w[kk] | (first[kk] ? 0x80000000u : 0u)));
                             nq += __popcll(m);
                         }
                     };
@@ -689,23 +779,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
                 GLOBAL int32_t* t = cur;
                 cur = nxt;
                 nxt = t;
+                t = cur_h;
+                cur_h = nxt_h;
+                nxt_h = t;
                 qn = nq;
+                if (B && qn > qcd) n_spill += (unsigned long long)(qn - qcd);
                 wave_fence();
             }
             pos = hi;
         }
 
         // ---- finish the row: diagonal, copy to the pool
-        if (ln == 0) rowb[rcount] = s;
+        if (ln == 0) rput(rcount, s);
         rcount += 1;
+        if (B && rcount > rcd) n_spill += (unsigned long long)(rcount - rcd);
         slot_fence();
         unsigned long long off = 0;
         if (ln == 0) off = atomicAdd(a.pool_tail, (unsigned long long)rcount);
         off = __shfl(off, 0, 64);
         const bool fits = (int64_t)(off + rcount) <= a.pool_cap;
         GLOBAL int32_t* pool = gbl(a.pool);
-        if (fits)
-            for (int32_t i = ln; i < rcount; i += 64) pool[off + i] = ld_coherent(&rowb[i]);
+        if (fits || B)
+            for (int32_t i = ln; i < rcount; i += 64) {
+                const int32_t v = rget(i);
+                if (fits) pool[off + i] = v;
+                // every set bit of a U word belongs to this source: clear the word
+                if (B && v > s) ub[v >> 5] = 0u;
+            }
+        if (B && n_spill && ln == 0) atomicAdd(&a.jstats[j].spilled, n_spill);
         if (ln == 0) {
             a.row_off[grow] = fits ? (int64_t)off : -1;
             a.row_cnt[grow] = rcount;
@@ -1236,7 +1337,7 @@ __global__ __launch_bounds__(64 * NW) void k_traverse_wg(TraverseArgs a) {
         const GLOBAL int32_t* ci = gbl(a.jobs[j].col_idx);
         const int64_t grow = a.jobs[j].row_base + s;
 
-        if (epoch >= emax) {
+        if (epoch >= emax || (a.flags & GSOFA_RESET_LABELS)) {
             for (int64_t i = tid; i < (int64_t)R; i += 64 * NW) lab[i] = kInf;
             epoch = 0;
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -1540,25 +1641,183 @@ __global__ __launch_bounds__(64 * NW) void k_traverse_wg(TraverseArgs a) {
     }
 }
 
+// ------------------------------------------- one thread per source (fill2)
+//
+// The comparison baseline of the Evaluation section's fill2 study: the fill2
+// threshold search run with one GPU thread per source row and no parallelism
+// inside a source. Thresholds (vertices of the structure below the source) are
+// taken in increasing order from a per-thread binary min-heap; from each, a
+// depth-first search walks the unvisited vertices below it; an unvisited
+// vertex above the threshold reached that way is in the structure (every
+// intermediate of its path is at most the threshold, which is below both ends)
+// and, if below the source, becomes a later threshold. Every vertex is visited
+// at most once per source, so the edges scanned are exactly the algorithmic
+// ones. Per-thread state uses the slot layout: visit stamps in the label array,
+// the heap in the first worklist, the search stack in the second, the row
+// buffer as in k_traverse.
+__global__ __launch_bounds__(256) void k_fill2_thread(TraverseArgs a) {
+    const int32_t slot = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (slot >= a.nslots) return;
+    uint8_t* sb = a.slots + (int64_t)slot * a.lay.bytes_per_slot;
+    uint32_t* stamp = (uint32_t*)(sb + a.lay.off_lab);
+    int32_t* heap = (int32_t*)(sb + a.lay.off_qa);
+    int32_t* stk = (int32_t*)(sb + a.lay.off_qb);
+    int32_t* rowb = (int32_t*)(sb + a.lay.off_row);
+    uint32_t* meta = (uint32_t*)(sb + a.lay.off_meta);
+    uint32_t epoch = meta[0];
+    const int64_t N = a.lay.N;
+
+    for (;;) {
+        const unsigned long long k = atomicAdd(a.item_counter, 1ull);
+        if (k >= (unsigned long long)a.nitems) break;
+        int32_t j, s;
+        if (a.item_rows) {
+            const int64_t gr = a.item_rows[k];
+            j = a.row_job ? a.row_job[gr] : 0;
+            s = (int32_t)(gr - a.jobs[j].row_base);
+        } else {
+            if (a.item_job) {
+                j = a.item_job[k];
+            } else {
+                int32_t lo = 0, hi = a.njobs - 1;
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (a.jobs[mid].item_base <= (int64_t)k) lo = mid;
+                    else hi = mid - 1;
+                }
+                j = lo;
+            }
+            s = a.jobs[j].n - 1 - (int32_t)((int64_t)k - a.jobs[j].item_base);
+        }
+        const int32_t* rp = a.jobs[j].row_ptr;
+        const int32_t* ci = a.jobs[j].col_idx;
+        const int64_t grow = a.jobs[j].row_base + s;
+        // stamps start at kInf (never an epoch); restart the count long before
+        if (epoch >= 0xFFFFFFF0u) {
+            for (int64_t i = 0; i < N; ++i) stamp[i] = 0u;
+            epoch = 0;
+        }
+        ++epoch;
+        stamp[s] = epoch;
+        int32_t rcount = 0, lcount = 0, ndiag = 0;
+        int64_t hn = 0;
+        bool dup = false;
+        unsigned long long e_alg = (unsigned long long)(rp[s + 1] - rp[s]);
+        uint32_t n_thr = 0;
+        auto heap_push = [&](int32_t x) {
+            int64_t i = hn++;
+            while (i > 0) {
+                const int64_t p = (i - 1) >> 1;
+                if (heap[p] <= x) break;
+                heap[i] = heap[p];
+                i = p;
+            }
+            heap[i] = x;
+        };
+        auto heap_pop = [&]() -> int32_t {
+            const int32_t top = heap[0];
+            const int32_t x = heap[--hn];
+            int64_t i = 0;
+            for (;;) {
+                int64_t c = 2 * i + 1;
+                if (c >= hn) break;
+                if (c + 1 < hn && heap[c + 1] < heap[c]) ++c;
+                if (heap[c] >= x) break;
+                heap[i] = heap[c];
+                i = c;
+            }
+            if (hn > 0) heap[i] = x;
+            return top;
+        };
+        // the source row's own entries
+        for (int32_t e = rp[s]; e < rp[s + 1]; ++e) {
+            const int32_t w = ci[e];
+            if (w == s) {
+                ++ndiag;
+                continue;
+            }
+            if (stamp[w] == epoch) {
+                dup = true;
+                continue;
+            }
+            stamp[w] = epoch;
+            rowb[rcount++] = w;
+            if (w < s) {
+                heap_push(w);
+                ++lcount;
+            }
+        }
+        // thresholds in increasing order
+        while (hn > 0) {
+            const int32_t t = heap_pop();
+            ++n_thr;
+            int64_t sp = 0;
+            stk[sp++] = t;
+            while (sp > 0) {
+                const int32_t x = stk[--sp];
+                const int32_t xs = rp[x], xe = rp[x + 1];
+                e_alg += (unsigned long long)(xe - xs);
+                for (int32_t e = xs; e < xe; ++e) {
+                    const int32_t w = ci[e];
+                    if (stamp[w] == epoch) continue;
+                    stamp[w] = epoch;
+                    if (w > t) {
+                        rowb[rcount++] = w;
+                        if (w < s) {
+                            heap_push(w);
+                            ++lcount;
+                        }
+                    } else {
+                        stk[sp++] = w;
+                    }
+                }
+            }
+        }
+        rowb[rcount++] = s;
+        const unsigned long long off = atomicAdd(a.pool_tail, (unsigned long long)rcount);
+        const bool fits = (int64_t)(off + rcount) <= a.pool_cap;
+        if (fits)
+            for (int32_t i = 0; i < rcount; ++i) a.pool[off + i] = rowb[i];
+        a.row_off[grow] = fits ? (int64_t)off : -1;
+        a.row_cnt[grow] = rcount;
+        a.row_lcnt[grow] = lcount;
+        if (!fits) atomicOr(&a.jstats[j].err, kErrOverflow);
+        if (dup || ndiag > 1) atomicOr(&a.jstats[j].err, kErrDuplicate);
+        if (a.row_stats)
+            a.row_stats[grow] = RowStat{e_alg, e_alg, n_thr, ndiag > 0 ? 0x80000000u : 0u};
+    }
+    meta[0] = epoch;
+}
+
 int32_t traverse_resident_slots(int cus, int mapping) {
     // resident blocks per CU, queried once per mapping
-    static std::atomic<int> known[5] = {{-1}, {-1}, {-1}, {-1}, {-1}};
-    const bool wave_map = mapping == 0 || mapping == 3 || mapping == 4;
-    if (mapping >= 0 && mapping < 5) {
+    static std::atomic<int> known[6] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
+    const bool wave_map = mapping == 0 || mapping == 3 || mapping == 4 || mapping == 5;
+    if (mapping >= 0 && mapping < 6) {
         const int b = known[mapping].load();
         if (b > 0) return b * (wave_map ? kTravWaves : 1) * cus;
     }
     int blocks = 0;
     hipError_t e;
+    if (mapping == 6) {
+        // one thread per source: resident threads
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_fill2_thread, 256, 0);
+        if (e != hipSuccess || blocks <= 0) {
+            (void)hipGetLastError();
+            blocks = 1;
+        }
+        return blocks * 256 * cus;
+    }
     if (mapping == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse8, 64 * kTravWaves, 0);
     else if (mapping == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse_wg<16>, 64 * 16, 0);
     else if (mapping == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse_wg<8>, 64 * 8, 0);
-    else if (mapping == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse<7>, 64 * kTravWaves, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse<8>, 64 * kTravWaves, 0);
+    else if (mapping == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse<7, false>, 64 * kTravWaves, 0);
+    else if (mapping == 5) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse<6, true>, 64 * kTravWaves, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_traverse<8, false>, 64 * kTravWaves, 0);
     if (e != hipSuccess || blocks <= 0) {
         (void)hipGetLastError();
         blocks = 1;
-    } else if (mapping >= 0 && mapping < 5) {
+    } else if (mapping >= 0 && mapping < 6) {
         known[mapping].store(blocks);
     }
     return blocks * (wave_map ? kTravWaves : 1) * cus;
@@ -1566,7 +1825,9 @@ int32_t traverse_resident_slots(int cus, int mapping) {
 
 hipError_t launch_traverse(const TraverseArgs& a, hipStream_t st) {
     if (a.nslots <= 0 || a.nitems <= 0) return hipSuccess;
-    if (a.mapping == 1) {
+    if (a.mapping == 6) {
+        hipLaunchKernelGGL(k_fill2_thread, dim3((unsigned)((a.nslots + 255) / 256)), dim3(256), 0, st, a);
+    } else if (a.mapping == 1) {
         hipLaunchKernelGGL(k_traverse_wg<16>, dim3(a.nslots), dim3(64 * 16), 0, st, a);
     } else if (a.mapping == 2) {
         hipLaunchKernelGGL(k_traverse_wg<8>, dim3(a.nslots), dim3(64 * 8), 0, st, a);
@@ -1575,10 +1836,13 @@ hipError_t launch_traverse(const TraverseArgs& a, hipStream_t st) {
         hipLaunchKernelGGL(k_traverse8, dim3(blocks), dim3(64 * kTravWaves), 0, st, a);
     } else if (a.mapping == 4) {
         const int blocks = (a.nslots + kTravWaves - 1) / kTravWaves;
-        hipLaunchKernelGGL(k_traverse<7>, dim3(blocks), dim3(64 * kTravWaves), 0, st, a);
+        hipLaunchKernelGGL((k_traverse<7, false>), dim3(blocks), dim3(64 * kTravWaves), 0, st, a);
+    } else if (a.mapping == 5) {
+        const int blocks = (a.nslots + kTravWaves - 1) / kTravWaves;
+        hipLaunchKernelGGL((k_traverse<6, true>), dim3(blocks), dim3(64 * kTravWaves), 0, st, a);
     } else {
         const int blocks = (a.nslots + kTravWaves - 1) / kTravWaves;
-        hipLaunchKernelGGL(k_traverse<8>, dim3(blocks), dim3(64 * kTravWaves), 0, st, a);
+        hipLaunchKernelGGL((k_traverse<8, false>), dim3(blocks), dim3(64 * kTravWaves), 0, st, a);
     }
     return hipGetLastError();
 }

@@ -214,6 +214,15 @@ def test_full_rows_span_several_sort_chunks(g):
     {"flags": 0x800, "window": 253}, {"flags": 0x800, "window": 200, "concurrent_sources": 5},
     {"flags": 0x800 | 0x20}, {"flags": 0x800 | 0x10},
     {"flags": 0x1000}, {"flags": 0x1000, "window": 3}, {"flags": 0x1000, "concurrent_sources": 7},
+    # label reset before every source (ablation of the value-range scheme)
+    {"flags": 0x10000}, {"flags": 0x10000 | 0x1000}, {"flags": 0x10000 | 0x80},
+    # one thread per source (fill2 comparison baseline)
+    {"flags": 0x8000}, {"flags": 0x8000, "concurrent_sources": 5}, {"flags": 0x8000 | 0x2},
+    # memory-budget mode: bands, U bitmap, host spill of worklists and row buffers
+    {"flags": 0x4000}, {"flags": 0x4000, "queue_cap": 64},
+    {"flags": 0x4000 | 0x10, "queue_cap": 64, "window": 3},
+    {"flags": 0x4000 | 0x20, "queue_cap": 100},
+    {"flags": 0x4000 | 0x10000, "queue_cap": 64, "concurrent_sources": 6},
 ], ids=str)
 def test_knobs_do_not_change_results(g, kw):
     m = synth.stencil(27, (11, 10, 9), nd=True, seed=21)
