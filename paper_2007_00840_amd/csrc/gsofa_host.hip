@@ -661,6 +661,7 @@ struct Plan {
     uint32_t flags;
     int64_t budget;
     int32_t queue_cap;  // memory-budget mode: device entries per worklist and row buffer
+    int32_t slot_div;   // the tuner's choice of sources in flight: planned count / slot_div
     bool window_auto;   // window span, mapping and sources in flight are the tuner's
     bool allow_trials;  // the tuner may time trial launches in this call
 };
@@ -719,14 +720,20 @@ struct TuneKey {
 struct TuneChoice {
     int mapping;     // 0 32-bit labels (eight wavefronts per SIMD), 4 the same at seven, 3 byte states
     int32_t window;  // threshold-window span
+    uint32_t flags;  // extra flags: GSOFA_NO_LINE95 (the access-order check switched off)
+    int32_t div;     // sources in flight: the planned count divided by div (#C)
 };
 
 constexpr TuneChoice kTuneCandidates[] = {
     // order is a prior: a later candidate replaces the best only if 5 % faster.
     // Seven wavefronts per SIMD with window 8 comes second: where window 8 wins
     // clearly (the 1000^2 9-point stencil) it also wins at seven by ~4 %, which
-    // the margin would hide if it came after window 8 at eight.
-    {0, 16}, {4, 8}, {0, 32}, {0, 64}, {0, 8}, {4, 16}, {3, 16},
+    // the margin would hide if it came after window 8 at eight. The last four
+    // are the paper's other two ablations as tuner dimensions: line 9.5 off
+    // (Section 4, access-order paragraph) and half the sources in flight
+    // (#C, the chunk-size study of the Evaluation section).
+    {0, 16, 0, 1}, {4, 8, 0, 1}, {0, 32, 0, 1}, {0, 64, 0, 1}, {0, 8, 0, 1}, {4, 16, 0, 1}, {3, 16, 0, 1},
+    {0, 16, GSOFA_NO_LINE95, 1}, {4, 8, GSOFA_NO_LINE95, 1}, {0, 16, 0, 2}, {4, 8, 0, 2},
 };
 constexpr int kTuneSamplesPerSlot = 24;
 
@@ -734,6 +741,14 @@ std::mutex g_tune_mu;
 std::map<TuneKey, TuneChoice>& tune_table() {
     static auto* t = new std::map<TuneKey, TuneChoice>();
     return *t;
+}
+
+// sources in flight divided by d, in whole blocks of four wavefronts
+int64_t div_slots(int64_t ns, int32_t d) {
+    if (d <= 1) return ns;
+    int64_t r = ns / d;
+    if (r > 4) r = r / 4 * 4;
+    return std::max<int64_t>(r, 1);
 }
 
 int ceil_log2(int64_t v) {
@@ -958,6 +973,8 @@ struct Engine {
                 if (it != tune_table().end()) {
                     mapping = it->second.mapping;
                     plan.window = it->second.window;
+                    plan.flags |= it->second.flags;
+                    plan.slot_div = it->second.div;
                     found = true;
                 }
             }
@@ -968,11 +985,13 @@ struct Engine {
                 t_tune = now_ms() - tt0;
                 mapping = c.mapping;
                 plan.window = c.window;
+                plan.flags = (plan.flags & ~(uint32_t)GSOFA_NO_LINE95) | c.flags;
+                plan.slot_div = c.div;
                 std::lock_guard<std::mutex> lk(g_tune_mu);
                 tune_table()[key] = c;
             }
         }
-        const int64_t nslots = budget_mode ? 0 : plan_slots(mapping);
+        const int64_t nslots = budget_mode ? 0 : div_slots(plan_slots(mapping), plan.slot_div);
 
         int64_t pool_cap = pool_estimate(nrows, total_nnz);
         if (!budget_mode) {
@@ -1528,7 +1547,11 @@ struct Engine {
                     PlanSlots plan_slots) {
         const int64_t R = plan_slots(0);
         const int64_t S = std::min<int64_t>(items, std::max<int64_t>(R * kTuneSamplesPerSlot, 1));
-        PinnedBuf h_s(4 * (size_t)S);
+        // the sample, and every other entry of it for the candidates with half
+        // the sources in flight (the same number of sources per slot, so the
+        // tail weighs the same; candidates are compared by edges per second)
+        const int64_t S2 = std::max<int64_t>(S / 2, 1);
+        PinnedBuf h_s(4 * (size_t)(S + S2));
         int32_t* smp = h_s.as<int32_t>();
         int32_t q = 0;
         for (int64_t i = 0; i < S; ++i) {
@@ -1536,10 +1559,12 @@ struct Engine {
             while (q + 1 < nj && jt[q + 1].item_base <= k) ++q;
             smp[i] = (int32_t)(jt[q].row_base + (jt[q].n - 1 - (k - jt[q].item_base)));
         }
-        DBuf d_s(4 * (size_t)S), tcnt(64), tjst(sizeof(JobStats) * (size_t)std::max(nj, 1));
+        for (int64_t i = 0; i < S2; ++i) smp[S + i] = smp[std::min<int64_t>(2 * i, S - 1)];
+        DBuf d_s(4 * (size_t)(S + S2)), tcnt(64), tjst(sizeof(JobStats) * (size_t)std::max(nj, 1));
         DBuf t_off(8 * (size_t)std::max<int64_t>(nrows, 1)), t_cnt(4 * (size_t)std::max<int64_t>(nrows, 1)),
-            t_lcnt(4 * (size_t)std::max<int64_t>(nrows, 1));
-        chk(hipMemcpyAsync(d_s.p, h_s.p, 4 * (size_t)S, hipMemcpyHostToDevice, st));
+            t_lcnt(4 * (size_t)std::max<int64_t>(nrows, 1)),
+            t_rs(sizeof(RowStat) * (size_t)std::max<int64_t>(nrows, 1));
+        chk(hipMemcpyAsync(d_s.p, h_s.p, 4 * (size_t)(S + S2), hipMemcpyHostToDevice, st));
         DBuf d_rj;
         if (nj > 1) {
             d_rj = DBuf(4 * (size_t)std::max<int64_t>(nrows, 1));
@@ -1550,9 +1575,10 @@ struct Engine {
         const int64_t room = (budget - fixed - R * lay.bytes_per_slot) / 4 / 3;
         const int64_t pcap = std::max<int64_t>(std::min<int64_t>(want_pool, room), 1 << 16);
         DBuf tpool(4 * (size_t)pcap);
+        PinnedBuf h_js(sizeof(JobStats) * (size_t)std::max(nj, 1));
         EventSet ev;
         TuneChoice best = kTuneCandidates[0];
-        float best_ms = 0;
+        double best_rate = 0;
         bool have = false;
         // The first candidate runs once untimed: the first launch on a new slot
         // set also pays for touching its memory, which made that candidate lose
@@ -1560,17 +1586,17 @@ struct Engine {
         constexpr int kCand = (int)(sizeof(kTuneCandidates) / sizeof(kTuneCandidates[0]));
         for (int t = -1; t < kCand; ++t) {
             const TuneChoice& c = kTuneCandidates[t < 0 ? 0 : t];
-            const int64_t ns = plan_slots(c.mapping);
+            const int64_t ns = div_slots(plan_slots(c.mapping), c.div);
             auto ss = take_slots(lay, (int32_t)ns, c.mapping == 3 ? 1 : 0, st);
             TraverseArgs ta{};
             ta.jobs = d_jobs.as<Job>();
             ta.njobs = nj;
             ta.nslots = (int32_t)std::min<int64_t>(ns, ss->nslots);
-            ta.nitems = S;
-            ta.item_rows = d_s.as<int32_t>();
+            ta.nitems = c.div == 2 ? S2 : S;
+            ta.item_rows = d_s.as<int32_t>() + (c.div == 2 ? S : 0);
             ta.row_job = d_rj.as<int32_t>();
             ta.item_job = nullptr;
-            ta.row_stats = nullptr;
+            ta.row_stats = t_rs.as<RowStat>();
             ta.item_counter = tcnt.as<unsigned long long>();
             ta.slots = ss->buf.as<uint8_t>();
             ta.lay = ss->lay;
@@ -1582,21 +1608,27 @@ struct Engine {
             ta.pool_cap = pcap;
             ta.jstats = tjst.as<JobStats>();
             ta.window = c.window;
-            ta.flags = plan.flags;
+            ta.flags = (plan.flags & ~(uint32_t)GSOFA_NO_LINE95) | c.flags;
             ta.mapping = c.mapping;
             chk(launch_zero_i32(tcnt.as<int32_t>(), 16, st));
             chk(launch_zero_i32(tjst.as<int32_t>(), (int64_t)(sizeof(JobStats) / 4) * nj, st));
+            chk(launch_zero_i32(t_rs.as<int32_t>(), (int64_t)(sizeof(RowStat) / 4) * nrows, st));
             chk(hipEventRecord(ev[0], st));
             chk(launch_traverse(ta, st));
             chk(hipEventRecord(ev[1], st));
+            chk(launch_job_stats(d_jobs.as<Job>(), nj, N, t_rs.as<RowStat>(), tjst.as<JobStats>(), st));
+            chk(hipMemcpyAsync(h_js.p, tjst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, st));
             chk(hipStreamSynchronize(st));
             give_slots(std::move(ss));
             if (t < 0) continue;
             float ms = 0;
             chk(hipEventElapsedTime(&ms, ev[0], ev[1]));
-            if (!have || ms < best_ms * 0.95f) {
+            double edges = 0;
+            for (int32_t jj = 0; jj < nj; ++jj) edges += (double)h_js.as<JobStats>()[jj].edges_alg;
+            const double rate = edges / std::max(1e-3, (double)ms);
+            if (!have || rate > best_rate * 1.05) {
                 best = c;
-                best_ms = ms;
+                best_rate = rate;
                 have = true;
             }
         }
@@ -1637,6 +1669,7 @@ Plan make_plan(const gsofa_opts* o) {
     p.window_auto = false;
     p.allow_trials = true;
     p.queue_cap = 0;
+    p.slot_div = 1;
     if (o) {
         p.flags = o->flags;
         p.budget = o->mem_budget_bytes;
