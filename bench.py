@@ -43,13 +43,17 @@ def traversal_source_hash():
     return hashlib.sha256(src[:end] if end >= 0 else src).hexdigest()[:16]
 
 
-def recorded_traffic(kernel, mapping, window, sources):
+PROFILE_OF_WORKLOAD = {"3d": "k_traverse_64cube_27pt.md", "2d": "k_traverse_1000sq_9pt.md",
+                       "batch": "k_traverse_batch4096.md"}
+
+
+def recorded_traffic(kernel, mapping, window, sources, workload="3d"):
     """HBM bytes per launch of the traversal kernel from the rocprofv3 PMC record
     in profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings),
     or None when no record matches this kernel source and configuration."""
     import re
     here = os.path.dirname(os.path.abspath(__file__))
-    rec = os.path.join(here, "profiles", "k_traverse_64cube_27pt.md")
+    rec = os.path.join(here, "profiles", PROFILE_OF_WORKLOAD[workload])
     try:
         sha = traversal_source_hash()
         text = open(rec).read()
@@ -66,22 +70,63 @@ def recorded_traffic(kernel, mapping, window, sources):
     return None
 
 
-def cpu_baseline(m, stride):
-    """The oracle (fill2 search, all host threads) on every stride-th row."""
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(m, stride, threads=None):
+    """The oracle (fill2 search; all host threads unless given) on every
+    stride-th row."""
     import numpy as np
     import oracle
     rows = np.arange(m.n - 1, -1, -stride, dtype=np.int32)
-    threads = oracle.default_threads()
+    threads = threads or oracle.default_threads()
     t0 = time.perf_counter()
     cnt, lcnt, edges, ptr, ent = oracle.rows_struct(m.n, m.row_ptr, m.col_idx, rows, threads)
     dt = time.perf_counter() - t0
     e = int(edges.sum())
     return {"value": e / dt / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
+            "cpu_model": host_cpu_model(),
             "sample": f"{len(rows)} of {m.n} rows (every {stride}th, from the last), "
-                      f"{e:.3e} algorithmic edges in {dt:.1f} s"}
+                      f"{e:.3e} algorithmic edges in {dt:.2f} s"}
 
 
-def bench_batch(g, torch, synth, reps):
+def cpu_baseline_batch(mats, every, threads=None):
+    """The oracle on every `every`-th matrix of the batch, one call per matrix,
+    all host threads unless given; reported as GTEPS and matrices/s."""
+    import oracle
+    threads = threads or oracle.default_threads()
+    sub = mats[::every]
+    t0 = time.perf_counter()
+    e = 0
+    for m in sub:
+        e += int(oracle.rows_struct(m.n, m.row_ptr, m.col_idx, None, threads)[2].sum())
+    dt = time.perf_counter() - t0
+    return {"value": e / dt / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
+            "matrices_per_s": round(len(sub) / dt, 2), "cpu_model": host_cpu_model(),
+            "sample": f"{len(sub)} of {len(mats)} matrices (every {every}th), "
+                      f"{e:.3e} algorithmic edges in {dt:.2f} s"}
+
+
+def roofline(e_alg, t_trav_ms, mapping, window, sources, workload):
+    """Algorithmic HBM rate of the traversal kernel against the 8 TB/s peak
+    (8 B per algorithmic edge), with the PMC traffic record if one matches."""
+    kern = KERNEL_OF_MAPPING.get(mapping, "k_traverse<8>")
+    achieved = BYTES_PER_EDGE * e_alg / (t_trav_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": recorded_traffic(kern, mapping, window, sources, workload),
+            "kernel": kern, "bytes_per_unit": BYTES_PER_EDGE, "unit_count": e_alg,
+            "kernel_ms": round(t_trav_ms, 3)}
+
+
+def bench_batch(g, torch, synth, reps, cpu=True):
     """The 4,096-matrix batch (config 4): one gsofa_batch call against one
     gsofa_symbolic call per matrix, inputs and results in device memory."""
     import numpy as np
@@ -131,7 +176,16 @@ def bench_batch(g, torch, synth, reps):
     t_single = time.perf_counter() - t0
     log(f"batch: {t_batch * 1e3:.1f} ms per batch, one call per matrix {t_single * 1e3:.1f} ms, "
         f"edges_alg {e_alg:.3e}, phases {phases}")
+    roof = roofline(e_alg, phases["t_traverse_ms"], phases["mapping"], phases["window"],
+                    phases["concurrent_sources"], "batch")
+    base = base1 = None
+    if cpu:
+        log("batch: cpu baseline (oracle on every 16th matrix, all threads; every 64th, one thread)")
+        base = cpu_baseline_batch(mats, 16)
+        base1 = cpu_baseline_batch(mats, 64, threads=1)
+        log(f"batch cpu: {base} / one thread {base1}")
     return {"matrices": len(mats), "sum_n": int(sum(m.n for m in mats)), "edges_alg": e_alg,
+            "roofline": roof, "cpu_baseline": base, "cpu_baseline_1thread": base1,
             "ms_per_batch": round(t_batch * 1e3, 3),
             "eager_ms_per_batch": round(t_eager * 1e3, 3),
             "graph_counters": list(g.graph_counters()),
@@ -146,16 +200,25 @@ def bench_batch(g, torch, synth, reps):
 def bench_ablations(g, torch, synth, m, rp, ci):
     """The paper's ablations on the headline workload, one call each after a
     warm-up: the access-order check off (line 9.5), the paper's breadth-first
-    frontier order instead of windows, 32-bit labels vs byte states, and the
-    window span; results are identical, time and revisits differ."""
+    frontier order instead of windows, 32-bit labels vs byte states, the window
+    span, the label array reset before every source instead of the value-range
+    scheme (maxId re-initialisation, Section 4), and the memory-budget mode at
+    16, 5 and 1 GB of source-slot state (the budgets of the paper's space
+    study). Results are identical; time, revisits and sources in flight differ."""
     stream = torch.cuda.current_stream().cuda_stream
     cases = [("windowed, window 16 (default)", dict(window=16, flags=g.MAP_WAVE32)),
              ("windowed, window 64", dict(window=64, flags=g.MAP_WAVE32)),
              ("access-order check off (line 9.5)", dict(window=16, flags=g.MAP_WAVE32 | g.NO_LINE95)),
              ("breadth-first order (paper)", dict(flags=g.MAP_WAVE32 | g.LEVEL_ORDER)),
-             ("byte states, window 16", dict(window=16, flags=g.MAP_BYTE))]
+             ("byte states, window 16", dict(window=16, flags=g.MAP_BYTE)),
+             ("labels reset before every source (no maxId re-init scheme)",
+              dict(window=16, flags=g.MAP_WAVE32 | g.RESET_LABELS))]
+    for gb in (16, 5, 1):
+        cases.append((f"memory budget {gb} GB (bands, host spill)",
+                      dict(window=16, flags=g.BUDGET_MODE, mem_budget_bytes=gb << 30)))
     out = []
     ref = None
+    base_ms = None
     for name, kw in cases:
         kw = dict(kw)
         kw["flags"] |= g.RESULT_ON_DEVICE | g.NO_TUNE
@@ -168,15 +231,90 @@ def bench_ablations(g, torch, synth, m, rp, ci):
         torch.cuda.synchronize()
         if ref is None:
             ref = fills
-        row = {"case": name, "t_traverse_ms": round(st["t_traverse_ms"], 3), "edges_alg": st["edges_alg"],
+            base_ms = st["t_traverse_ms"]
+        row = {"case": name, "t_traverse_ms": round(st["t_traverse_ms"], 3),
+               "slowdown_vs_default": round(st["t_traverse_ms"] / base_ms, 3), "edges_alg": st["edges_alg"],
                "edges_gpu": st["edges_gpu"], "revisit_ratio": round(st["edges_gpu"] / max(st["edges_alg"], 1), 4),
-               "levels": st["iterations"], "windows": st["windows"], "same_fills": fills == ref}
+               "levels": st["iterations"], "windows": st["windows"],
+               "concurrent_sources": st["concurrent_sources"], "launches": st["launches"],
+               "spilled_entries": st["spilled_entries"], "same_fills": fills == ref}
         log(f"ablation: {row}")
         out.append(row)
     return out
 
 
-def bench_2d(g, torch, synth, steps):
+def bench_baselines(g, torch, synth, gp_cap_s):
+    """Comparison baselines on the three single-matrix workloads: the fill2
+    search with one GPU thread per source (the paper's GPU fill2 comparison)
+    against the default kernel, and the CPU Gilbert-Peierls column-by-column
+    symbolic factorisation (one thread, stopped after gp_cap_s seconds on the
+    larger workloads; then the columns done are reported)."""
+    import baselines
+    out = []
+    stream = torch.cuda.current_stream().cuda_stream
+    for cfg in (1, 2, 3):
+        m = synth.config(cfg)
+        rp = torch.from_numpy(m.row_ptr).cuda()
+        ci = torch.from_numpy(m.col_idx).cuda()
+        row = {"config": cfg, "workload": m.desc, "n": m.n}
+        for name, flags in (("default", 0), ("thread_per_source_fill2", g.MAP_THREAD)):
+            kw = dict(flags=flags | g.RESULT_ON_DEVICE | g.NO_TUNE, stream=stream)
+            if flags == 0 or cfg == 1:
+                # warm-up (the one-thread baseline runs for tens of seconds on the
+                # larger workloads, where a warm-up would change nothing)
+                r = g.symbolic(m.n, rp, ci, **kw)
+                r.free()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = g.symbolic(m.n, rp, ci, **kw)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+            row[name] = {"ms": round(ms, 3), "t_traverse_ms": round(r.stats["t_traverse_ms"], 3),
+                         "gteps": round(r.stats["edges_alg"] / ms / 1e6, 3),
+                         "concurrent_sources": r.stats["concurrent_sources"]}
+            row["edges_alg"] = r.stats["edges_alg"]
+            r.free()
+        row["default_speedup_vs_thread_per_source"] = round(
+            row["thread_per_source_fill2"]["ms"] / row["default"]["ms"], 2)
+        gp = baselines.gilbert_peierls(m.n, m.row_ptr, m.col_idx, time_limit_s=gp_cap_s)
+        row["cpu_gilbert_peierls"] = {"seconds": round(gp.seconds, 3), "columns_done": gp.cols_done,
+                                      "complete": gp.cols_done == m.n, "threads": 1,
+                                      "l_entries_scanned": gp.edges, "cpu_model": host_cpu_model()}
+        if gp.cols_done == m.n:
+            row["default_speedup_vs_cpu_gilbert_peierls"] = round(1e3 * gp.seconds / row["default"]["ms"], 1)
+        log(f"baselines: {row}")
+        out.append(row)
+    return out
+
+
+def bench_config1(g, torch, synth, steps, cpu=True):
+    """The tiny workload (40 x 40 5-point stencil, natural order): GPU time per
+    call and the oracle on all host threads and on one thread."""
+    m = synth.config(1)
+    rp = torch.from_numpy(m.row_ptr).cuda()
+    ci = torch.from_numpy(m.col_idx).cuda()
+    stream = torch.cuda.current_stream().cuda_stream
+    r = g.symbolic(m.n, rp, ci, flags=g.RESULT_ON_DEVICE, stream=stream)
+    r.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = g.symbolic(m.n, rp, ci, flags=g.RESULT_ON_DEVICE, stream=stream)
+        st = r.stats
+        r.free()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    out = {"workload": "2D 5-point stencil 40x40, natural order, drop 0.2, seed 1", "n": m.n,
+           "ms_per_call": round(ms, 3), "gteps": round(st["edges_alg"] / ms / 1e6, 3),
+           "edges_alg": st["edges_alg"], "t_traverse_ms": round(st["t_traverse_ms"], 3)}
+    if cpu:
+        out["cpu_baseline"] = cpu_baseline(m, 1)
+        out["cpu_baseline_1thread"] = cpu_baseline(m, 1, threads=1)
+    log(f"config 1: {out}")
+    return out
+
+
+def bench_2d(g, torch, synth, steps, cpu=True):
     """The 2D workload (9-point stencil on a 1000 x 1000 grid, nested
     dissection, drop 0.2): one warm-up call (tunes its size class), then
     `steps` timed calls, inputs and results in device memory."""
@@ -208,11 +346,16 @@ def bench_2d(g, torch, synth, steps):
            "t_emit_ms": round(sum(x["t_emit_ms"] for x in stats) / steps, 3),
            "window": stats[-1]["window"], "mapping": stats[-1]["mapping"],
            "concurrent_sources": stats[-1]["concurrent_sources"], "t_tune_ms_warmup": round(tune_ms, 3)}
+    out["roofline"] = roofline(e_alg, t_trav, stats[-1]["mapping"], stats[-1]["window"],
+                               stats[-1]["concurrent_sources"], "2d")
+    if cpu:
+        log("2d: cpu baseline (oracle on every row, all threads)")
+        out["cpu_baseline"] = cpu_baseline(m, 1)
     log(f"2d: {out}")
     return out
 
 
-def _serve_run(g, synth, trace, cap_s, mode, drain_s=0.0, max_inflight=8, max_outstanding=64):
+def _serve_run(g, synth, trace, cap_s, mode, drain_s=0.0, max_inflight=4, max_outstanding=64):
     """Offers the requests of the trace that arrive within cap_s seconds, on
     their arrival schedule, and waits up to drain_s more for them to finish.
     mode 'serve' uses the continuous-batching server, 'plain' one
@@ -313,7 +456,7 @@ def bench_serve(g, synth, cap_s, low_rate):
 
 # traversal kernel launched for each mapping code reported in the stats
 KERNEL_OF_MAPPING = {3: "k_traverse8", 0: "k_traverse<8>", 4: "k_traverse<7>", 2: "k_traverse_wg<8>",
-                     1: "k_traverse_wg<16>"}
+                     1: "k_traverse_wg<16>", 5: "k_traverse<6, true>", 6: "k_fill2_thread"}
 
 
 def main():
@@ -330,8 +473,12 @@ def main():
     ap.add_argument("--skip-ablations", action="store_true",
                     help="do not time the paper's ablations on the headline workload")
     ap.add_argument("--batch-reps", type=int, default=3, help="0 = skip the batch measurement")
-    ap.add_argument("--serve-seconds", type=float, default=20.0,
-                    help="wall cap of the request-stream measurement (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="arrivals offered and wall cap of the request-stream measurement, in seconds; "
+                         "60 offers the whole trace (0 = skip)")
+    ap.add_argument("--baselines-cap", type=float, default=15.0,
+                    help="seconds the CPU Gilbert-Peierls baseline may run per workload (0 = skip the "
+                         "comparison baselines)")
     ap.add_argument("--serve-low-rate", type=float, default=1.0,
                     help="requests/s of the drained low-rate request stream (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -392,14 +539,17 @@ def main():
     t_emit = sum(s["t_emit_ms"] for s in stats) / len(stats)
     t_sn = sum(s["t_supernode_ms"] for s in stats) / len(stats)
     gteps = e_alg / (ms * 1e-3) / 1e9
-    achieved = BYTES_PER_EDGE * e_alg / (t_trav * 1e-3) / 1e9
     log(f"steps: {ms:.1f} ms/step, traverse {t_trav:.1f} ms, emit {t_emit:.1f} ms, "
         f"supernode {t_sn:.1f} ms, {gteps:.1f} GTEPS")
 
     ablations = None if args.skip_ablations else bench_ablations(g, torch, synth, m, rp, ci)
-    twod = bench_2d(g, torch, synth, args.twod_steps) if args.twod_steps > 0 else None
+    cpu_legs = args.cpu_stride > 0
+    cfg1 = bench_config1(g, torch, synth, max(args.steps, 3), cpu_legs)
+    twod = bench_2d(g, torch, synth, args.twod_steps, cpu_legs) if args.twod_steps > 0 else None
     g.release_cache()  # the 2D workload's slot sets are not reused below
-    batch = bench_batch(g, torch, synth, args.batch_reps) if args.batch_reps > 0 else None
+    batch = bench_batch(g, torch, synth, args.batch_reps, cpu_legs) if args.batch_reps > 0 else None
+    base_cmp = bench_baselines(g, torch, synth, args.baselines_cap) if args.baselines_cap > 0 else None
+    g.release_cache()
     serve = bench_serve(g, synth, args.serve_seconds, args.serve_low_rate) if args.serve_seconds > 0 else None
 
     base = None
@@ -424,14 +574,8 @@ def main():
         "config": {"workload": "3D 27-point stencil 64x64x64, nested dissection, drop 0.2, seed 3",
                    "n": m.n, "nnz": m.nnz, "result": "device-resident L (CSC), U (CSR), supernodes",
                    "max_supernode": 128, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": recorded_traffic(KERNEL_OF_MAPPING.get(stats[-1]["mapping"], "k_traverse<8>"),
-                                                 stats[-1]["mapping"], stats[-1]["window"],
-                                                 stats[-1]["concurrent_sources"]),
-                     "kernel": KERNEL_OF_MAPPING.get(stats[-1]["mapping"], "k_traverse<8>"),
-                     "bytes_per_unit": BYTES_PER_EDGE,
-                     "unit_count": e_alg, "kernel_ms": round(t_trav, 3)},
+        "roofline": roofline(e_alg, t_trav, stats[-1]["mapping"], stats[-1]["window"],
+                             stats[-1]["concurrent_sources"], "3d"),
         "cpu_baseline": base,
         "edges_alg": e_alg,
         "edges_gpu": e_gpu,
@@ -444,7 +588,9 @@ def main():
         "window": stats[-1]["window"], "mapping": stats[-1]["mapping"],
         "t_tune_ms_warmup": round(max(s["t_tune_ms"] for s in warm_stats), 3) if warm_stats else 0.0,
         "ablations": ablations,
+        "workload_1": cfg1,
         "workload_2d": twod,
+        "baselines": base_cmp,
         "batch": batch,
         "serve": serve,
     }

@@ -318,6 +318,64 @@ PinnedPool& pinned_pool() {
     return *p;
 }
 
+// Pinned host memory for the worklist / row-buffer overflow of memory-budget
+// mode: one block kept between calls (pinning tens of GB takes seconds), owned
+// by one call at a time; a call that finds it taken or too small pins its own,
+// and the larger of the two stays cached.
+class SpillCache {
+   public:
+    struct Block {
+        void* p = nullptr;
+        size_t bytes = 0;
+    };
+    Block take(size_t bytes) {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            if (cached_.p && cached_.bytes >= bytes) {
+                Block b = cached_;
+                cached_ = Block{};
+                return b;
+            }
+        }
+        Block b;
+        b.bytes = (bytes + 4095) & ~size_t(4095);
+        chk(hipHostMalloc(&b.p, b.bytes, hipHostMallocDefault));
+        return b;
+    }
+    void give(Block b) {
+        if (!b.p) return;
+        Block drop;
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            if (!cached_.p || cached_.bytes < b.bytes) {
+                drop = cached_;
+                cached_ = b;
+            } else {
+                drop = b;
+            }
+        }
+        if (drop.p) (void)hipHostFree(drop.p);
+    }
+    void release() {
+        Block drop;
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            drop = cached_;
+            cached_ = Block{};
+        }
+        if (drop.p) (void)hipHostFree(drop.p);
+    }
+
+   private:
+    std::mutex mu_;
+    Block cached_;
+};
+
+SpillCache& spill_cache() {
+    static SpillCache* c = new SpillCache();  // lives until process end
+    return *c;
+}
+
 struct PinnedBuf {
     void* p = nullptr;
     explicit PinnedBuf(size_t b) : p(pinned_pool().take(std::max<size_t>(b, 8))) {}
@@ -974,7 +1032,7 @@ struct Engine {
                     mapping = it->second.mapping;
                     plan.window = it->second.window;
                     plan.flags |= it->second.flags;
-                    plan.slot_div = it->second.div;
+                    plan.slot_div = plan.nslots > 0 ? 1 : it->second.div;
                     found = true;
                 }
             }
@@ -1072,44 +1130,68 @@ struct Engine {
             // order of decreasing local id
             if (rows.empty()) return;
             const int64_t R5 = traverse_resident_slots(di.cus, 5);
+            // plan the bands: [lo, hi) of local ids, layout, sources in flight
+            struct Band {
+                size_t pos, end;
+                SlotLayout lay;
+                int64_t ns;
+            };
+            std::vector<Band> bands;
+            size_t spill_entries = 1;
+            {
+                size_t pos = 0;
+                int64_t hi = (int64_t)local[0] + 1;
+                while (pos < rows.size()) {
+                    const SlotLayout lb = slot_layout_budget(N, hi, plan.queue_cap > 0 ? plan.queue_cap : 8192);
+                    int64_t C = std::min<int64_t>(R5, slot_budget / lb.bytes_per_slot);
+                    C = std::min<int64_t>(C, kSpillHostBytes / std::max<int64_t>(4 * lb.h_stride, 1));
+                    if (plan.nslots > 0) C = std::min<int64_t>(C, plan.nslots);
+                    if (C < 1) throw Status{GSOFA_ENOMEM};
+                    const int64_t lo = (C >= R5 || hi <= 4096) ? 0 : hi / 2;
+                    size_t end = pos;
+                    while (end < rows.size() && local[end] >= lo) ++end;
+                    int64_t ns = std::min<int64_t>(C, (int64_t)(end - pos));
+                    if (ns > 4) ns = ns / 4 * 4;
+                    if (end > pos) {
+                        bands.push_back(Band{pos, end, lb, ns});
+                        spill_entries = std::max<size_t>(spill_entries, (size_t)(ns * lb.h_stride));
+                    }
+                    pos = end;
+                    hi = lo;
+                }
+            }
             DBuf d_rows(4 * rows.size());
             chk(hipMemcpyAsync(d_rows.p, rows.data(), 4 * rows.size(), hipMemcpyHostToDevice, st));
-            size_t pos = 0;
-            int64_t hi = (int64_t)local[0] + 1;
-            while (pos < rows.size()) {
-                const SlotLayout lb = slot_layout_budget(N, hi, plan.queue_cap > 0 ? plan.queue_cap : 8192);
-                int64_t C = std::min<int64_t>(R5, slot_budget / lb.bytes_per_slot);
-                C = std::min<int64_t>(C, kSpillHostBytes / std::max<int64_t>(4 * lb.h_stride, 1));
-                if (plan.nslots > 0) C = std::min<int64_t>(C, plan.nslots);
-                if (C < 1) throw Status{GSOFA_ENOMEM};
-                const int64_t lo = (C >= R5 || hi <= 4096) ? 0 : hi / 2;
-                size_t end = pos;
-                while (end < rows.size() && local[end] >= lo) ++end;
-                int64_t ns = std::min<int64_t>(C, (int64_t)(end - pos));
-                if (ns > 4) ns = ns / 4 * 4;
-                DBuf sl((size_t)ns * (size_t)lb.bytes_per_slot);
-                chk(launch_init_slots(sl.as<uint8_t>(), (int32_t)ns, lb, st));
-                PinnedBuf spill((size_t)std::max<int64_t>(ns * lb.h_stride, 1) * 4);
+            // one spill area serves every band (bands run one after another)
+            struct SpillHold {
+                SpillCache::Block b;
+                hipStream_t st;
+                ~SpillHold() {
+                    (void)hipStreamSynchronize(st);
+                    (void)hipGetLastError();
+                    spill_cache().give(b);
+                }
+            } spill{spill_cache().take(4 * spill_entries), st};
+            for (const Band& bd : bands) {
+                DBuf sl((size_t)bd.ns * (size_t)bd.lay.bytes_per_slot);
+                chk(launch_init_slots(sl.as<uint8_t>(), (int32_t)bd.ns, bd.lay, st));
                 TraverseArgs tb = ta;
                 tb.slots = sl.as<uint8_t>();
-                tb.lay = lb;
-                tb.nslots = (int32_t)ns;
-                tb.item_rows = d_rows.as<int32_t>() + pos;
-                tb.nitems = (int64_t)(end - pos);
+                tb.lay = bd.lay;
+                tb.nslots = (int32_t)bd.ns;
+                tb.item_rows = d_rows.as<int32_t>() + bd.pos;
+                tb.nitems = (int64_t)(bd.end - bd.pos);
                 tb.item_job = nullptr;
                 tb.row_job = nj > 1 ? d_row_job.as<int32_t>() : nullptr;
-                tb.host_spill = spill.as<int32_t>();
+                tb.host_spill = static_cast<int32_t*>(spill.b.p);
                 tb.mapping = 5;
                 chk(launch_zero_i32(counters.as<int32_t>(), 2, st));  // the item counter only
                 chk(launch_traverse(tb, st));
                 ++band_launches;
-                budget_max_c = std::max<int32_t>(budget_max_c, (int32_t)ns);
-                budget_peak_slots = std::max<int64_t>(budget_peak_slots, ns * lb.bytes_per_slot);
-                // the band's slots and spill area are released next
-                chk(hipStreamSynchronize(st));
-                pos = end;
-                hi = lo;
+                budget_max_c = std::max<int32_t>(budget_max_c, (int32_t)bd.ns);
+                budget_peak_slots = std::max<int64_t>(budget_peak_slots, bd.ns * bd.lay.bytes_per_slot);
             }
+            chk(hipStreamSynchronize(st));
         };
         // local id of a global row (matrices in the user's order, row_base increasing)
         auto local_of = [&](int32_t r) -> int32_t {
@@ -1694,7 +1776,7 @@ int check_opts(const gsofa_opts* o) {
 std::mutex g_api_mu;  // one call at a time per process for the plain entry points
 
 int run_engine(std::vector<MatIn> mats, const gsofa_opts* o, std::vector<gsofa_result*>& outs,
-               bool allow_trials = true) {
+               bool allow_trials = true, bool tuned_with_slots = false) {
     Engine eng;
     eng.mats = std::move(mats);
     eng.plan = make_plan(o);
@@ -1706,7 +1788,9 @@ int run_engine(std::vector<MatIn> mats, const gsofa_opts* o, std::vector<gsofa_r
         N = std::max<int64_t>(N, m.n);
         rows += std::max<int32_t>(m.n, 0);
     }
-    eng.plan.window_auto = eng.plan.window <= 0 && eng.plan.nslots <= 0 &&
+    // the server gives a request its sources in flight and still takes the
+    // cached mapping and window of its size class
+    eng.plan.window_auto = eng.plan.window <= 0 && (eng.plan.nslots <= 0 || tuned_with_slots) &&
                            (eng.plan.flags & (GSOFA_MAP_WAVE32 | GSOFA_MAP_WAVE32_7 | GSOFA_MAP_WG8 | GSOFA_MAP_WG16 | GSOFA_MAP_BYTE |
                                               GSOFA_LEVEL_ORDER | GSOFA_NO_LINE95 | GSOFA_BUDGET_MODE | GSOFA_MAP_THREAD |
                                               GSOFA_RESET_LABELS)) == 0;
@@ -1853,6 +1937,7 @@ extern "C" GSOFA_API int gsofa_release_cache(void) {
     std::lock_guard<std::mutex> g(g_api_mu);
     drop_idle_slots();
     cache().release();
+    spill_cache().release();
     return GSOFA_OK;
 }
 
@@ -1897,6 +1982,7 @@ struct gsofa_server {
         std::vector<int32_t> rp, ci;
         int64_t est;
         int32_t nslots;  // sources in flight for this request
+        int32_t passed = 0;  // times a later request was admitted before this one
     };
     std::deque<Req> queue;
     int32_t inflight = 0;
@@ -1937,6 +2023,21 @@ constexpr int32_t kServeSmallRows = 65536;
 constexpr size_t kServeMaxGroup = 64;
 constexpr int64_t kServeGroupRows = 1 << 20;
 
+// Admission order: the oldest queued request that fits the memory left, so a
+// large request waiting for memory does not block smaller ones behind it; once
+// the oldest has been passed kServeMaxPassed times, nothing passes it any more
+// and it is admitted as soon as its memory is free.
+constexpr int32_t kServeMaxPassed = 32;
+
+long serve_pick(const gsofa_server* s) {
+    if (s->queue.empty()) return -1;
+    const auto fits = [&](const gsofa_server::Req& r) { return s->mem_in_use + r.est <= s->budget; };
+    if (s->queue.front().passed >= kServeMaxPassed) return fits(s->queue.front()) ? 0 : -1;
+    for (size_t i = 0; i < s->queue.size(); ++i)
+        if (fits(s->queue[i])) return (long)i;
+    return -1;
+}
+
 void serve_worker(gsofa_server* s, int sid) {
     (void)hipSetDevice(s->device);
     for (;;) {
@@ -1944,13 +2045,16 @@ void serve_worker(gsofa_server* s, int sid) {
         int64_t grp_est = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
+            long pick = -1;
             s->cv.wait(lk, [&] {
                 if (s->queue.empty()) return s->closing;
-                return s->mem_in_use + s->queue.front().est <= s->budget;
+                pick = serve_pick(s);
+                return pick >= 0;
             });
             if (s->queue.empty()) return;  // closing and drained
-            grp.push_back(std::move(s->queue.front()));
-            s->queue.pop_front();
+            if (pick > 0) s->queue.front().passed++;
+            grp.push_back(std::move(s->queue[(size_t)pick]));
+            s->queue.erase(s->queue.begin() + pick);
             grp_est = grp[0].est;
             if (grp[0].n <= kServeSmallRows) {
                 // later small requests that fit the memory budget join, in arrival order
@@ -1979,8 +2083,9 @@ void serve_worker(gsofa_server* s, int sid) {
         std::vector<MatIn> mats;
         for (auto& r : grp) mats.push_back(MatIn{r.n, r.rp.data(), r.ci.data()});
         std::vector<gsofa_result*> outs;
-        // no tuner trials inside a request: they would add to its latency
-        const int rc = run_engine(std::move(mats), &o, outs, false);
+        // no tuner trials inside a request (they would add to its latency), but
+        // the size class's cached choice of mapping and window applies
+        const int rc = run_engine(std::move(mats), &o, outs, false, true);
         std::lock_guard<std::mutex> g(s->mu);
         for (size_t i = 0; i < grp.size(); ++i) {
             gsofa_result* res = i < outs.size() ? outs[i] : nullptr;
