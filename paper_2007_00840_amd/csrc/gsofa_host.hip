@@ -786,11 +786,14 @@ constexpr TuneChoice kTuneCandidates[] = {
     // order is a prior: a later candidate replaces the best only if 5 % faster.
     // Seven wavefronts per SIMD with window 8 comes second: where window 8 wins
     // clearly (the 1000^2 9-point stencil) it also wins at seven by ~4 %, which
-    // the margin would hide if it came after window 8 at eight. The last four
+    // the margin would hide if it came after window 8 at eight. Windows 4 and 2
+    // cut revisits on 2D stencils (1.31x edges at window 8, 1.12x at 4, 1.03x
+    // at 2 on the 1000^2 9-point stencil; 249 -> 216 ms at 4). The last four
     // are the paper's other two ablations as tuner dimensions: line 9.5 off
     // (Section 4, access-order paragraph) and half the sources in flight
     // (#C, the chunk-size study of the Evaluation section).
     {0, 16, 0, 1}, {4, 8, 0, 1}, {0, 32, 0, 1}, {0, 64, 0, 1}, {0, 8, 0, 1}, {4, 16, 0, 1}, {3, 16, 0, 1},
+    {0, 4, 0, 1}, {0, 2, 0, 1}, {4, 4, 0, 1},
     {0, 16, GSOFA_NO_LINE95, 1}, {4, 8, GSOFA_NO_LINE95, 1}, {0, 16, 0, 2}, {4, 8, 0, 2},
 };
 constexpr int kTuneSamplesPerSlot = 24;
