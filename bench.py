@@ -126,7 +126,7 @@ def roofline(e_alg, t_trav_ms, mapping, window, sources, workload):
             "kernel_ms": round(t_trav_ms, 3)}
 
 
-def bench_batch(g, torch, synth, reps, cpu=True):
+def bench_batch(g, torch, synth, reps, cpu=True, single=True, window=0, extra_flags=0):
     """The 4,096-matrix batch (config 4): one gsofa_batch call against one
     gsofa_symbolic call per matrix, inputs and results in device memory."""
     import numpy as np
@@ -136,7 +136,7 @@ def bench_batch(g, torch, synth, reps, cpu=True):
         f"sum n = {sum(m.n for m in mats)}")
     dev = [(m.n, torch.from_numpy(m.row_ptr).cuda(), torch.from_numpy(m.col_idx).cuda()) for m in mats]
     stream = torch.cuda.current_stream().cuda_stream
-    flags = g.RESULT_ON_DEVICE
+    flags = g.RESULT_ON_DEVICE | extra_flags
     def phases_of(st):
         ph = {k: round(st[k], 3) for k in ("t_traverse_ms", "t_emit_ms", "t_supernode_ms", "t_total_ms")}
         ph["concurrent_sources"] = st["concurrent_sources"]
@@ -144,7 +144,7 @@ def bench_batch(g, torch, synth, reps, cpu=True):
         ph["mapping"] = st["mapping"]
         return ph
 
-    res = g.batch(dev, flags=flags, stream=stream)  # warm-up (tuning, output-pool sizing)
+    res = g.batch(dev, flags=flags, stream=stream, window=window)  # warm-up (tuning, output-pool sizing)
     e_alg = sum(r.stats["edges_alg"] for r in res)
     warm = phases_of(res[0].stats)
     warm["t_tune_ms"] = round(res[0].stats["t_tune_ms"], 3)
@@ -154,26 +154,28 @@ def bench_batch(g, torch, synth, reps, cpu=True):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        res = g.batch(dev, flags=flags, stream=stream)
+        res = g.batch(dev, flags=flags, stream=stream, window=window)
         phases = phases_of(res[0].stats)  # HIP-event phase times of the timed call
         for r in res:
             r.free()
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
     # the same batch launched kernel by kernel instead of one graph per phase
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        res = g.batch(dev, flags=flags | g.EAGER, stream=stream)
-        for r in res:
+    t_eager = t_single = float("nan")
+    if single:
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res = g.batch(dev, flags=flags | g.EAGER, stream=stream, window=window)
+            for r in res:
+                r.free()
+        torch.cuda.synchronize()
+        t_eager = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for n, rp, ci in dev:
+            r = g.symbolic(n, rp, ci, flags=flags, stream=stream)
             r.free()
-    torch.cuda.synchronize()
-    t_eager = (time.perf_counter() - t0) / reps
-    t0 = time.perf_counter()
-    for n, rp, ci in dev:
-        r = g.symbolic(n, rp, ci, flags=flags, stream=stream)
-        r.free()
-    torch.cuda.synchronize()
-    t_single = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t_single = time.perf_counter() - t0
     log(f"batch: {t_batch * 1e3:.1f} ms per batch, one call per matrix {t_single * 1e3:.1f} ms, "
         f"edges_alg {e_alg:.3e}, phases {phases}")
     roof = roofline(e_alg, phases["t_traverse_ms"], phases["mapping"], phases["window"],
@@ -314,7 +316,7 @@ def bench_config1(g, torch, synth, steps, cpu=True):
     return out
 
 
-def bench_2d(g, torch, synth, steps, cpu=True):
+def bench_2d(g, torch, synth, steps, cpu=True, window=0, extra_flags=0):
     """The 2D workload (9-point stencil on a 1000 x 1000 grid, nested
     dissection, drop 0.2): one warm-up call (tunes its size class), then
     `steps` timed calls, inputs and results in device memory."""
@@ -323,14 +325,15 @@ def bench_2d(g, torch, synth, steps, cpu=True):
     rp = torch.from_numpy(m.row_ptr).cuda()
     ci = torch.from_numpy(m.col_idx).cuda()
     stream = torch.cuda.current_stream().cuda_stream
-    r = g.symbolic(m.n, rp, ci, flags=g.RESULT_ON_DEVICE, stream=stream)
+    kw = dict(flags=g.RESULT_ON_DEVICE | extra_flags, window=window, stream=stream)
+    r = g.symbolic(m.n, rp, ci, **kw)
     tune_ms = r.stats["t_tune_ms"]
     r.free()
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        r = g.symbolic(m.n, rp, ci, flags=g.RESULT_ON_DEVICE, stream=stream)
+        r = g.symbolic(m.n, rp, ci, **kw)
         stats.append(r.stats)
         fills = r.fills
         r.free()
@@ -484,6 +487,8 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--only", choices=["2d", "batch"], default=None,
+                    help="time only this workload (with --window / --flags pinned; for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the symbolic engine runs on one GPU per process; --gpus must be 1"}))
@@ -503,6 +508,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": nbytes}))
+        return
+    if args.only == "2d":
+        print(json.dumps(bench_2d(g, torch, synth, max(args.twod_steps, 1), False, args.window, args.flags)))
+        return
+    if args.only == "batch":
+        print(json.dumps(bench_batch(g, torch, synth, max(args.batch_reps, 1), False, False, args.window,
+                                     args.flags), default=str))
         return
     m = synth.config(3)
     log(f"workload: {m.desc} n={m.n} nnz={m.nnz}")

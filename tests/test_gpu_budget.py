@@ -92,20 +92,25 @@ def test_budget_mode_output_pool_regrowth(g):
     """A low running fill ratio (after a tridiagonal call) under-sizes the
     output pool of a high-fill call: overflowing rows are redone in budget
     mode after the pool grows."""
-    n = 300000
-    rp = np.arange(0, 3 * n + 1, 3, dtype=np.int32)[: n + 1].copy()
-    ci = np.stack([np.arange(n) - 1, np.arange(n), np.arange(n) + 1], axis=1).ravel()
-    keep = (ci >= 0) & (ci < n)
-    cnt = keep.reshape(n, 3).sum(axis=1)
+    import time
+    n = 100000
+    i = np.arange(n)
+    cols = [np.stack([i - 1, i, i + 1], axis=1).ravel()]
+    ci = cols[0][(cols[0] >= 0) & (cols[0] < n)].astype(np.int32)
+    cnt = np.full(n, 3)
+    cnt[0] = cnt[-1] = 2
     rp = np.zeros(n + 1, dtype=np.int32)
     np.cumsum(cnt, out=rp[1:])
-    ci = ci[keep].astype(np.int32)
-    g.symbolic(n, rp, ci)
+    t0 = time.time()
+    g.symbolic(n, rp, ci, flags=g.NO_TUNE)
+    _say(f"tridiagonal call done in {time.time() - t0:.1f} s")
     m = synth.stencil(27, (22, 22, 22), nd=True, seed=405)
     ref = oracle.symbolic(m.n, m.row_ptr, m.col_idx)
+    t0 = time.time()
     res = g.symbolic(m.n, m.row_ptr, m.col_idx, flags=g.BUDGET_MODE, queue_cap=256)
+    _say(f"budget call done in {time.time() - t0:.1f} s, launches={res.stats['launches']}")
     _same(res, ref)
-    _say(f"regrowth launches={res.stats['launches']}")
+    assert res.stats["launches"] >= 2  # the bands, then the redone rows
 
 
 def test_budget_below_one_slot_is_enomem(g):
