@@ -447,7 +447,7 @@ def bench_serve(g, synth, cap_s, low_rate):
     out["throughput_vs_plain"] = round(a / b, 3) if b else None
     if low_rate > 0:
         low = synth.serve_trace(rate=low_rate)
-        low_cap = cap_s / 2
+        low_cap = min(cap_s / 2, 10.0)
         res = {"rate_per_s": low_rate, "cap_s": low_cap, "drain_s": 3 * low_cap}
         res["continuous_batching"] = _serve_run(g, synth, low, low_cap, "serve", drain_s=3 * low_cap)
         log(f"serve at {low_rate}/s: {res['continuous_batching']}")
