@@ -825,14 +825,34 @@ struct EngineOut {
 
 // Per-launch fill-ratio memory used to size the output pool of later calls.
 std::atomic<double> g_fill_ratio{48.0};
+// The same per size class (the tuner's key): a batch of small 3D stencils fills
+// more per stored entry than a large 2D stencil, and a pool sized from the other
+// class's ratio overflowed and cost a second traversal pass (418 ms on the
+// 4,096-matrix batch after the 1000^2 stencil).
+std::mutex g_fill_mu;
+std::map<TuneKey, double>& fill_ratios() {
+    static auto* m = new std::map<TuneKey, double>();
+    return *m;
+}
+double fill_ratio_for(const TuneKey& k) {
+    std::lock_guard<std::mutex> g(g_fill_mu);
+    auto it = fill_ratios().find(k);
+    return it != fill_ratios().end() ? it->second : 48.0;
+}
+void note_fill_ratio(const TuneKey& k, double r) {
+    std::lock_guard<std::mutex> g(g_fill_mu);
+    fill_ratios()[k] = r;
+    g_fill_ratio.store(r);
+}
 
 // Device bytes a launch needs besides slots and output pool: inputs, per-row
 // arrays, assembly buffers, scratch.
 int64_t fixed_bytes(int64_t nrows, int64_t nnz) { return nrows * 40 + nnz * 8 + (64ll << 20); }
 
 // Output-pool entries expected for nnz stored entries.
-int64_t pool_estimate(int64_t nrows, int64_t nnz) {
-    return std::max<int64_t>((int64_t)(g_fill_ratio.load() * (double)nnz * 1.15) + nrows, 1 << 20);
+int64_t pool_estimate(int64_t nrows, int64_t nnz, double ratio = -1.0) {
+    if (ratio <= 0) ratio = g_fill_ratio.load();
+    return std::max<int64_t>((int64_t)(ratio * (double)nnz * 1.15) + nrows, 1 << 20);
 }
 
 // Budget under which the planner below gives nslots slots and the expected
@@ -1024,9 +1044,10 @@ struct Engine {
         };
         int mapping = choose_mapping(plan.flags, plan.window);
         double t_tune = 0;
+        const TuneKey key{di.cus, ceil_log2(N), ceil_log2(std::max<int64_t>(total_nnz * 4 / std::max<int64_t>(nrows, 1), 1)),
+                          nj > 1 ? ceil_log2(nj) : 0};
+        const double fill_ratio = fill_ratio_for(key);
         if (plan.window_auto) {
-            const TuneKey key{di.cus, ceil_log2(N), ceil_log2(std::max<int64_t>(total_nnz * 4 / std::max<int64_t>(nrows, 1), 1)),
-                              nj > 1 ? ceil_log2(nj) : 0};
             bool found = false;
             {
                 std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1054,7 +1075,7 @@ struct Engine {
         }
         const int64_t nslots = budget_mode ? 0 : div_slots(plan_slots(mapping), plan.slot_div);
 
-        int64_t pool_cap = pool_estimate(nrows, total_nnz);
+        int64_t pool_cap = pool_estimate(nrows, total_nnz, fill_ratio);
         if (!budget_mode) {
             const int64_t pool_room = (budget - fixed - nslots * lay.bytes_per_slot) / 4 / 3;
             pool_cap = std::max<int64_t>(std::min<int64_t>(pool_cap, pool_room), nrows + 1024);
@@ -1313,7 +1334,7 @@ struct Engine {
         chk(hipEventRecord(ev[1], st));
         if (slots) give_slots(std::move(slots));
         if (total_nnz > 0)
-            g_fill_ratio.store(std::max(4.0, (double)*h_tail / (double)total_nnz));
+            note_fill_ratio(key, std::max(4.0, (double)*h_tail / (double)total_nnz));
 
         // ---- phase 2: counts -> row pointers of U and L, and the totals
         DBuf scan_scr(8 * (size_t)scan_scratch_elems(nrows + 1) + 64);
@@ -1656,7 +1677,12 @@ struct Engine {
             chk(launch_row_job(d_jobs.as<Job>(), nj, N, d_rj.as<int32_t>(), st));
         }
         // scratch output pool for the sample; rows that do not fit are only flagged
-        const int64_t want_pool = pool_estimate(nrows, total_nnz) / std::max<int64_t>(items, 1) * S * 2 + (1 << 20);
+        const int64_t want_pool =
+            pool_estimate(nrows, total_nnz, fill_ratio_for(TuneKey{device_info().cus, ceil_log2(N),
+                                                                  ceil_log2(std::max<int64_t>(total_nnz * 4 / std::max<int64_t>(nrows, 1), 1)),
+                                                                  nj > 1 ? ceil_log2(nj) : 0})) /
+                std::max<int64_t>(items, 1) * S * 2 +
+            (1 << 20);
         const int64_t room = (budget - fixed - R * lay.bytes_per_slot) / 4 / 3;
         const int64_t pcap = std::max<int64_t>(std::min<int64_t>(want_pool, room), 1 << 16);
         DBuf tpool(4 * (size_t)pcap);

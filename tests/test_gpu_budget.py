@@ -89,21 +89,22 @@ def test_budget_mode_batch_and_device_io(g):
 
 
 def test_budget_mode_output_pool_regrowth(g):
-    """A low running fill ratio (after a tridiagonal call) under-sizes the
-    output pool of a high-fill call: overflowing rows are redone in budget
-    mode after the pool grows."""
+    """A low fill ratio recorded for a size class (a banded matrix of the same
+    size and row length, which does not fill) under-sizes the output pool of a
+    high-fill call of that class: overflowing rows are redone in budget mode
+    after the pool grows."""
     import time
-    n = 100000
-    i = np.arange(n)
-    cols = [np.stack([i - 1, i, i + 1], axis=1).ravel()]
-    ci = cols[0][(cols[0] >= 0) & (cols[0] < n)].astype(np.int32)
-    cnt = np.full(n, 3)
-    cnt[0] = cnt[-1] = 2
+    n, bw = 10000, 10
+    i = np.repeat(np.arange(n), 2 * bw + 1)
+    j = i + np.tile(np.arange(-bw, bw + 1), n)
+    keep = (j >= 0) & (j < n)
+    ci = j[keep].astype(np.int32)
     rp = np.zeros(n + 1, dtype=np.int32)
-    np.cumsum(cnt, out=rp[1:])
+    np.cumsum(np.bincount(i[keep], minlength=n), out=rp[1:])
     t0 = time.time()
-    g.symbolic(n, rp, ci, flags=g.NO_TUNE)
-    _say(f"tridiagonal call done in {time.time() - t0:.1f} s")
+    band = g.symbolic(n, rp, ci, flags=g.NO_TUNE)
+    assert band.fills == 0
+    _say(f"banded call done in {time.time() - t0:.1f} s")
     m = synth.stencil(27, (22, 22, 22), nd=True, seed=405)
     ref = oracle.symbolic(m.n, m.row_ptr, m.col_idx)
     t0 = time.time()
