@@ -62,6 +62,11 @@ typedef enum {
     GSOFA_ENOTFOUND = 6   /* serve: unknown or already collected ticket          */
 } gsofa_status;
 
+/* Largest supported matrix order. Per-source label arrays are addressed with
+ * 32-bit byte offsets (4 bytes per vertex), so n must stay below 2^30; a larger
+ * n is rejected with GSOFA_EINVAL by every entry point. */
+#define GSOFA_MAX_N 1073741823
+
 /* option flags */
 #define GSOFA_NO_SUPERNODES     0x1u  /* skip supernode detection (nsuper = 0)        */
 #define GSOFA_L_CSR             0x2u  /* return L row-wise (skip the transpose)       */

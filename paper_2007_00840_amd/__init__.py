@@ -42,6 +42,7 @@ EXPORTED = ["gsofa_symbolic", "gsofa_batch", "gsofa_serve_open", "gsofa_serve_su
             "gsofa_release_cache", "gsofa_graph_counters", "gsofa_memory_counters",
             "gsofa_symbolic_noalloc"]
 NOALLOC_SCRATCH_BYTES = 128 << 20
+MAX_N = (1 << 30) - 1  # largest supported matrix order
 
 
 class GsofaError(RuntimeError):

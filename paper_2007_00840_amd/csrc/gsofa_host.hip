@@ -654,7 +654,7 @@ DeviceInfo device_info() {
 // ------------------------------------------------------------ input checks
 
 int check_csr_host(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<uint32_t>& stamp) {
-    if (n < 0) return GSOFA_EINVAL;
+    if (n < 0 || n > GSOFA_MAX_N) return GSOFA_EINVAL;
     if (n == 0) return GSOFA_OK;
     if (!rp || rp[0] != 0) return GSOFA_EINVAL;
     for (int32_t i = 0; i < n; ++i)
@@ -1876,7 +1876,7 @@ extern "C" GSOFA_API int gsofa_symbolic(int32_t n, const int32_t* row_ptr, const
     if (!out) return GSOFA_EINVAL;
     int rc = check_opts(opts);
     if (rc != GSOFA_OK) return rc;
-    if (n < 0) return GSOFA_EINVAL;
+    if (n < 0 || n > GSOFA_MAX_N) return GSOFA_EINVAL;
     const bool on_dev = opts && (opts->flags & GSOFA_INPUT_ON_DEVICE);
     if (n > 0 && (!row_ptr || !col_idx)) {
         // col_idx may be NULL only for an empty pattern
@@ -1911,7 +1911,8 @@ extern "C" GSOFA_API int gsofa_batch(int32_t count, const gsofa_csr* mats, const
     std::vector<uint32_t> stamp;
     for (int32_t i = 0; i < count; ++i) {
         if (!on_dev) pre[i] = check_csr_host(mats[i].n, mats[i].row_ptr, mats[i].col_idx, stamp);
-        else if (mats[i].n < 0 || (mats[i].n > 0 && !mats[i].row_ptr)) pre[i] = GSOFA_EINVAL;
+        else if (mats[i].n < 0 || mats[i].n > GSOFA_MAX_N || (mats[i].n > 0 && !mats[i].row_ptr))
+            pre[i] = GSOFA_EINVAL;
     }
     std::vector<int32_t> idx;
     for (int32_t i = 0; i < count; ++i)

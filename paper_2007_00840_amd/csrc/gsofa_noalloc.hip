@@ -331,7 +331,7 @@ extern "C" GSOFA_API int gsofa_symbolic_noalloc(int32_t n, const int32_t* row_pt
                                                 const gsofa_opts* opts, int64_t* u_ptr, int32_t* u_idx,
                                                 int64_t u_cap, int64_t* l_ptr, int32_t* l_idx, int64_t l_cap,
                                                 int32_t* xsup, int32_t* supno, gsofa_counts* counts) {
-    if (!counts || n < 0 || !u_ptr || !l_ptr || u_cap < 0 || l_cap < 0) return GSOFA_EINVAL;
+    if (!counts || n < 0 || n > GSOFA_MAX_N || !u_ptr || !l_ptr || u_cap < 0 || l_cap < 0) return GSOFA_EINVAL;
     if (opts) {
         if (opts->struct_size != 0 && opts->struct_size < sizeof(gsofa_opts)) return GSOFA_EINVAL;
         if (opts->flags & ~kAllowed) return GSOFA_EINVAL;

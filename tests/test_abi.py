@@ -118,6 +118,28 @@ def test_bad_opts_rejected(g):
                               ctypes.byref(out)) == g.EINVAL
 
 
+def test_order_above_limit_rejected(g):
+    """n above GSOFA_MAX_N is refused before any array is read or any GPU call."""
+    txt = open(HEADER).read()
+    assert int(re.search(r"#define GSOFA_MAX_N (\d+)", txt).group(1)) == g.MAX_N == (1 << 30) - 1
+    lib = g.load()
+    rp = np.zeros(2, dtype=np.int32)
+    ci = np.zeros(1, dtype=np.int32)
+    out = ctypes.POINTER(g.Result)()
+    for flags in (0, g.INPUT_ON_DEVICE):
+        o = g.make_opts(flags=flags)
+        assert lib.gsofa_symbolic(g.MAX_N + 1, rp.ctypes.data, ci.ctypes.data, ctypes.byref(o),
+                                  ctypes.byref(out)) == g.EINVAL
+        assert not out
+    u_ptr = np.zeros(2, dtype=np.int64)
+    l_ptr = np.zeros(2, dtype=np.int64)
+    xs = np.zeros(2, dtype=np.int32)
+    c = g.Counts()
+    assert lib.gsofa_symbolic_noalloc(g.MAX_N + 1, rp.ctypes.data, ci.ctypes.data, None,
+                                      u_ptr.ctypes.data, None, 0, l_ptr.ctypes.data, None, 0,
+                                      xs.ctypes.data, xs.ctypes.data, ctypes.byref(c)) == g.EINVAL
+
+
 def test_batch_argument_errors(g):
     lib = g.load()
     assert lib.gsofa_batch(-1, None, None, None) == g.EINVAL
