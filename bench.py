@@ -457,6 +457,82 @@ def bench_serve(g, synth, cap_s, low_rate):
     return out
 
 
+def _admission_run(g, big, small, flags, gap_s=0.01):
+    """Two copies of a large request (none if big is None), then the small
+    requests one every gap_s seconds, on a server whose large requests fill
+    the device (4 workers, each lone large request with half the resident
+    wavefronts less a small reserve). Returns the small
+    requests' latencies (completion - submission) and the large ones'
+    completion times and traversal launches."""
+    import numpy as np
+    srv = g.Server(max_inflight=4, flags=flags, mem_budget_bytes=200 << 30)
+    t0 = time.perf_counter()
+    tb = [srv.submit(big.n, big.row_ptr, big.col_idx) for _ in range(2)] if big is not None else []
+    time.sleep(0.02)
+    sub, done, big_done, big_launches, st_of = {}, {}, {}, {}, {}
+    pending = set()
+    k = 0
+    nxt = time.perf_counter()
+    while len(done) < len(small) or len(big_done) < len(tb):
+        now = time.perf_counter()
+        if k < len(small) and now >= nxt:
+            m = small[k]
+            t = srv.submit(m.n, m.row_ptr, m.col_idx)
+            sub[t] = time.perf_counter()
+            pending.add(t)
+            k += 1
+            nxt += gap_s
+        for t in list(pending):
+            r = srv.poll(t, timeout_us=0)
+            if r is not None:
+                done[t] = time.perf_counter() - sub[t]
+                st_of[t] = (round(r.stats["t_total_ms"], 1), round(r.stats["t_traverse_ms"], 1))
+                pending.discard(t)
+        for t in tb:
+            if t not in big_done:
+                r = srv.poll(t, timeout_us=0)
+                if r is not None:
+                    big_done[t] = time.perf_counter() - t0
+                    big_launches[t] = r.stats["launches"]
+        if now - t0 > 60:
+            break
+        time.sleep(0.0002)
+    srv.close()
+    out = {"large_done_ms": sorted(round(1e3 * v, 1) for v in big_done.values()),
+           "large_launches": [big_launches[t] for t in tb if t in big_launches]}
+    if done:
+        lat = np.sort(np.array(list(done.values())))
+        pct = lambda q: round(1e3 * float(lat[min(len(lat) - 1, int(np.ceil(q * len(lat))) - 1)]), 2)
+        out.update({"small_completed": len(done), "small_p50_ms": pct(0.5), "small_p99_ms": pct(0.99),
+                    "small_max_ms": round(1e3 * float(lat[-1]), 2)})
+        # the slowest small requests: (submission after the start, latency, the
+        # engine call's wall time, its traversal time), ms
+        slow = sorted(done, key=lambda t: -done[t])[:5]
+        out["small_slowest"] = [(round(1e3 * (sub[t] - t0), 1), round(1e3 * done[t], 1)) + st_of[t]
+                                for t in slow]
+    return out
+
+
+def bench_admission(g, synth, big):
+    """Latency of small requests (4,096-matrix batch members, one every
+    10 ms) submitted while two large requests (the 64^3 27-point stencil) fill
+    the device: on an idle device, with the default server (a reserve of wave
+    slots, copies as the library's own small-workgroup kernels), and with the
+    large traversals also yielding their wave slots (GSOFA_SERVE_YIELD); the
+    large requests alone for their cost."""
+    small = [synth.batch_member(9000 + k) for k in range(60)]
+    out = {"large": f"2 x {big.desc}", "small": f"{len(small)} batch members, one every 10 ms"}
+    _admission_run(g, big, small[:8], 0)  # warm-up: size classes, slot sets
+    out["idle"] = _admission_run(g, None, small, 0)  # the small requests on an idle device
+    log(f"admission idle: {out['idle']}")
+    out["large_only"] = _admission_run(g, big, [], 0)  # the large requests without small ones
+    log(f"admission large only: {out['large_only']}")
+    for name, flags in (("default", 0), ("yield", g.SERVE_YIELD)):
+        out[name] = _admission_run(g, big, small, flags)
+        log(f"admission {name}: {out[name]}")
+    return out
+
+
 # traversal kernel launched for each mapping code reported in the stats
 KERNEL_OF_MAPPING = {3: "k_traverse8", 0: "k_traverse<8>", 4: "k_traverse<7>", 2: "k_traverse_wg<8>",
                      1: "k_traverse_wg<16>", 5: "k_traverse<6, true>", 6: "k_fill2_thread"}
@@ -487,7 +563,10 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
-    ap.add_argument("--only", choices=["2d", "batch"], default=None,
+    ap.add_argument("--admission", type=int, default=1,
+                    help="1 = measure small-request latency behind large requests with and "
+                         "without work-item admission (0 = skip)")
+    ap.add_argument("--only", choices=["2d", "batch", "admission"], default=None,
                     help="time only this workload (with --window / --flags pinned; for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -517,6 +596,9 @@ def main():
                                      args.flags), default=str))
         return
     m = synth.config(3)
+    if args.only == "admission":
+        print(json.dumps(bench_admission(g, synth, m)))
+        return
     log(f"workload: {m.desc} n={m.n} nnz={m.nnz}")
     rp = torch.from_numpy(m.row_ptr).cuda()
     ci = torch.from_numpy(m.col_idx).cuda()
@@ -563,6 +645,8 @@ def main():
     base_cmp = bench_baselines(g, torch, synth, args.baselines_cap) if args.baselines_cap > 0 else None
     g.release_cache()
     serve = bench_serve(g, synth, args.serve_seconds, args.serve_low_rate) if args.serve_seconds > 0 else None
+    if serve is not None and args.admission:
+        serve["admission"] = bench_admission(g, synth, m)
 
     base = None
     if args.cpu_stride > 0:

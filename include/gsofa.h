@@ -134,6 +134,15 @@ typedef enum {
  * source (O(n) per source) instead of moving to a fresh value range. Results
  * are unchanged. */
 #define GSOFA_RESET_LABELS      0x10000u
+/* Server: work-item admission. A large request's traversal (more than 65,536
+ * rows) gives its wave slots up when a request is admitted onto a full device:
+ * it takes no further source, finishes the ones it holds, and resumes from
+ * where it stopped once the new request's traversal is on the device (at most
+ * once per 20 ms). Results are unchanged. Off by default: the server already
+ * keeps a reserve of wave slots that large traversals never take, and a yield
+ * idles the large traversal until its slowest current source is done. Ignored
+ * outside the server. */
+#define GSOFA_SERVE_YIELD       0x20000u
 
 /* A CSR pattern: n rows, row_ptr[n+1], col_idx[row_ptr[n]]; host pointers
  * unless GSOFA_INPUT_ON_DEVICE is set. */
@@ -169,7 +178,9 @@ typedef struct {
     double t_tune_ms;           /* autotuner trial time spent in this call (0 if none)    */
     uint64_t spilled_entries;   /* worklist and row-buffer entries written to host memory
                                    (GSOFA_BUDGET_MODE; 0 otherwise)                       */
-    int32_t launches;           /* traversal launches (source-id bands in budget mode)    */
+    int32_t launches;           /* traversal launches (source-id bands in budget mode,
+                                   relaunches of a served request after it yielded,
+                                   pool-regrowth re-runs)                                 */
     int32_t pad_;
 } gsofa_stats;
 
@@ -262,7 +273,11 @@ GSOFA_API int gsofa_batch(int32_t count, const gsofa_csr* mats, const gsofa_opts
  * requests that fit (up to 64 and 2^20 rows together) and runs them as one
  * persistent launch, as gsofa_batch does. Admitted work runs concurrently on
  * the device and finished requests release their memory, which admits the
- * next. Requests never time tuner trials (cached choices or defaults).
+ * next. A request's traversal takes a share of the resident wavefronts less
+ * a reserve of 256 that kernels of requests admitted meanwhile run in; with
+ * GSOFA_SERVE_YIELD running large traversals also give their wave slots up to
+ * a request admitted onto a full device. Requests never time tuner trials
+ * (cached choices or defaults).
  *   serve_submit copies the CSR (host pointers) and returns a ticket.
  *     GSOFA_ECAPACITY if the request alone can never fit the budget.
  *   serve_poll waits up to timeout_us microseconds (0 = just test,

@@ -36,6 +36,7 @@ NO_TUNE = 0x2000
 BUDGET_MODE = 0x4000
 MAP_THREAD = 0x8000
 RESET_LABELS = 0x10000
+SERVE_YIELD = 0x20000
 
 EXPORTED = ["gsofa_symbolic", "gsofa_batch", "gsofa_serve_open", "gsofa_serve_submit",
             "gsofa_serve_poll", "gsofa_serve_close", "gsofa_result_free", "gsofa_strerror",

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -387,6 +388,15 @@ struct PinnedBuf {
     template <typename T>
     T* as() const { return static_cast<T*>(p); }
 };
+
+// Transfers of a call's small arrays run as copy kernels of this library
+// (256-thread workgroups, a few registers each). The runtime copies host and
+// device memory with kernels of 512- and 1,024-thread workgroups, which wait
+// for a compute unit with that much room, and there is none while persistent
+// traversals of other calls hold the device: a 2,000-row server request's
+// input upload waited 0.4 s behind two 64^3 traversals. Larger transfers keep
+// the runtime's copies.
+constexpr size_t kKernelCopyMax = 8u << 20;
 
 // ------------------------------------------------------------ HIP graphs
 //
@@ -890,12 +900,25 @@ __global__ void k_rebase_ptr(int32_t njobs, const int64_t* job_row_base, const i
         out[b + j + i] = g[b + i] - g0;
 }
 
+// A served request's link to the server's work-item admission. The traversal
+// launches poll `flag` (fine-grained host memory) before each work item; the
+// server sets it when it admits another request onto a full device, the launch
+// then stops taking items, and the engine relaunches from the work counter once
+// `before_resume` returns (the admitted request's traversal is enqueued by
+// then, or a bounded wait has passed). `enqueued` runs once the first traversal
+// launch of the call is on the stream, `finished` once the traversal is done.
+struct YieldHooks {
+    uint32_t* flag = nullptr;
+    std::function<void()> enqueued, finished, before_resume;
+};
+
 struct Engine {
     std::vector<MatIn> mats;
     bool on_device = false;
     gsofa_opts o{};
     Plan plan{};
     hipStream_t st = nullptr;
+    const YieldHooks* yh = nullptr;  // server requests only
 
     // outputs
     std::vector<gsofa_result*> results;
@@ -903,6 +926,22 @@ struct Engine {
     int run() {
         const double t0 = now_ms();
         StreamScope scope(st);
+        // staging blocks of this call's uploads; released (after the stream is
+        // idle) when the call ends
+        std::vector<std::unique_ptr<PinnedBuf>> staged;
+        auto h2d = [&](void* dst, const void* src, size_t bytes, hipStream_t s, bool src_pinned) {
+            if (bytes == 0) return;
+            if (bytes > kKernelCopyMax || bytes % 4 != 0) {
+                chk(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+                return;
+            }
+            if (!src_pinned) {
+                staged.push_back(std::make_unique<PinnedBuf>(bytes));
+                std::memcpy(staged.back()->p, src, bytes);
+                src = staged.back()->p;
+            }
+            chk(launch_copy_from_host(dst, src, bytes, s));
+        };
         const int32_t nj = (int32_t)mats.size();
         results.assign(nj, nullptr);
         std::vector<int> jstat(nj, GSOFA_OK);
@@ -927,12 +966,12 @@ struct Engine {
             }
             DBuf d_tab(sizeof(Job) * std::max(nj, 1)), d_last(8 * std::max(nj, 1));
             PinnedBuf h_last(8 * std::max(nj, 1));
-            chk(hipMemcpyAsync(d_tab.p, jobs.data(), sizeof(Job) * nj, hipMemcpyHostToDevice, st));
+            h2d(d_tab.p, jobs.data(), sizeof(Job) * nj, st, false);
             if (nj > 0)
                 hipLaunchKernelGGL(k_gather_last, dim3((nj + 255) / 256), dim3(256), 0, st, nj, d_tab.as<Job>(),
                                    d_last.as<int64_t>());
             chk(hipGetLastError());
-            chk(hipMemcpyAsync(h_last.p, d_last.p, 8 * nj, hipMemcpyDeviceToHost, st));
+            chk(launch_copy_to_host(h_last.p, d_last.p, 8 * nj, st));
             chk(hipStreamSynchronize(st));
             for (int32_t j = 0; j < nj; ++j) {
                 const int64_t last = h_last.as<int64_t>()[j];
@@ -967,9 +1006,8 @@ struct Engine {
                     sp[rp_off[j]] = 0;
                 }
             }
-            chk(hipMemcpyAsync(in_rp.p, sp, 4 * (size_t)rp_tot, hipMemcpyHostToDevice, st));
-            if (ci_tot > 0)
-                chk(hipMemcpyAsync(in_ci.p, sp + rp_tot, 4 * (size_t)ci_tot, hipMemcpyHostToDevice, st));
+            h2d(in_rp.p, sp, 4 * (size_t)rp_tot, st, true);
+            h2d(in_ci.p, sp + rp_tot, 4 * (size_t)ci_tot, st, true);
             chk(hipStreamSynchronize(st));
             for (int32_t j = 0; j < nj; ++j) {
                 jobs[j].row_ptr = in_rp.as<int32_t>() + rp_off[j];
@@ -996,15 +1034,16 @@ struct Engine {
             items += mats[j].n;
         }
         DBuf d_jobs(sizeof(Job) * std::max(nj, 1));
-        chk(hipMemcpyAsync(d_jobs.p, jt.data(), sizeof(Job) * nj, hipMemcpyHostToDevice, st));
+        h2d(d_jobs.p, jt.data(), sizeof(Job) * nj, st, false);
 
         if (on_device) {
             DBuf bad(4 * std::max(nj, 1));
             chk(launch_zero_i32(bad.as<int32_t>(), nj, st));
             chk(launch_validate(d_jobs.as<Job>(), nj, N, bad.as<int32_t>(), st));
-            std::vector<int32_t> hb(nj);
-            chk(hipMemcpyAsync(hb.data(), bad.p, 4 * nj, hipMemcpyDeviceToHost, st));
+            PinnedBuf h_bad(4 * (size_t)std::max(nj, 1));
+            chk(launch_copy_to_host(h_bad.p, bad.p, 4 * (size_t)nj, st));
             chk(hipStreamSynchronize(st));
+            const int32_t* hb = h_bad.as<int32_t>();
             for (int32_t q = 0; q < nj; ++q)
                 if (hb[q]) jstat[ord[q]] = GSOFA_EINVAL;
             bool any_bad = false;
@@ -1104,6 +1143,7 @@ struct Engine {
         JobStats* hst = h_stats.as<JobStats>();
         unsigned long long* h_tail =
             reinterpret_cast<unsigned long long*>(h_stats.as<char>() + sizeof(JobStats) * (size_t)std::max(nj, 1));
+        unsigned long long* h_items = h_tail + 1;  // work counter after the traversal
 
         // ev[0]/ev[4]: traversal phase; ev[1]..ev[3]: emit, supernode and column phases
         EventSet ev;
@@ -1143,6 +1183,7 @@ struct Engine {
         // buffers keep queue_cap entries on the device and spill the rest to
         // pinned host memory (external frontier management).
         int32_t band_launches = 0;
+        int32_t trav_launches = 1;  // default mode: the first launch, plus relaunches after yields
         int32_t budget_max_c = 0;
         int64_t budget_peak_slots = 0;
         const int64_t slot_budget =
@@ -1185,7 +1226,7 @@ struct Engine {
                 }
             }
             DBuf d_rows(4 * rows.size());
-            chk(hipMemcpyAsync(d_rows.p, rows.data(), 4 * rows.size(), hipMemcpyHostToDevice, st));
+            h2d(d_rows.p, rows.data(), 4 * rows.size(), st, false);
             // one spill area serves every band (bands run one after another)
             struct SpillHold {
                 SpillCache::Block b;
@@ -1239,8 +1280,8 @@ struct Engine {
                 }
             run_budget(rows, local);
             chk(launch_job_stats(d_jobs.as<Job>(), nj, N, row_stats.as<RowStat>(), jst.as<JobStats>(), st));
-            chk(hipMemcpyAsync(hst, jst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, st));
-            chk(hipMemcpyAsync(h_tail, counters.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, st));
+            chk(launch_copy_to_host(hst, jst.p, sizeof(JobStats) * nj, st));
+            chk(launch_copy_to_host(h_tail, counters.as<unsigned long long>() + 1, 8, st));
             chk(hipEventRecord(ev[4], st));
             chk(hipStreamSynchronize(st));
         } else {
@@ -1253,30 +1294,75 @@ struct Engine {
             }
             chk(launch_zero_i32(counters.as<int32_t>(), 16, s));
             chk(launch_zero_i32(jst.as<int32_t>(), (int64_t)(sizeof(JobStats) / 4) * nj, s));
+            ta.yield = yh ? yh->flag : nullptr;
             chk(launch_traverse(ta, s));
             chk(launch_job_stats(d_jobs.as<Job>(), nj, N, row_stats.as<RowStat>(), jst.as<JobStats>(), s));
-            chk(hipMemcpyAsync(hst, jst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, s));
-            chk(hipMemcpyAsync(h_tail, counters.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, s));
+            chk(launch_copy_to_host(hst, jst.p, sizeof(JobStats) * nj, s));
+            chk(launch_copy_to_host(h_tail, counters.as<unsigned long long>() + 1, 8, s));
+            chk(launch_copy_to_host(h_items, counters.as<unsigned long long>(), 8, s));
             ph.launch();
+            if (yh && yh->enqueued) yh->enqueued();
             chk(hipEventRecord(ev[4], st));
             chk(hipStreamSynchronize(st));
             ph.done();
+            // A launch asked to yield stopped taking work items: every item below
+            // the counter is done, relaunch for the rest. Two launches in a row
+            // that take nothing (the flag keeps being set) end the yielding.
+            int32_t idle = 0;
+            std::vector<int32_t> err_seen(ta.yield ? (size_t)nj : 0, 0);
+            while (ta.yield && *h_items < (unsigned long long)items) {
+                const unsigned long long before = *h_items;
+                // the statistics are summed again after the relaunch; error bits of
+                // rows done so far are kept on the host
+                for (int32_t q = 0; q < nj; ++q) err_seen[(size_t)q] |= hst[q].err;
+                if (yh->before_resume) yh->before_resume();
+                __atomic_store_n(yh->flag, 0u, __ATOMIC_RELEASE);
+                if (idle >= 2) ta.yield = nullptr;
+                chk(launch_zero_i32(jst.as<int32_t>(), (int64_t)(sizeof(JobStats) / 4) * nj, st));
+                chk(launch_traverse(ta, st));
+                ++trav_launches;
+                chk(launch_job_stats(d_jobs.as<Job>(), nj, N, row_stats.as<RowStat>(), jst.as<JobStats>(), st));
+                chk(launch_copy_to_host(hst, jst.p, sizeof(JobStats) * nj, st));
+                chk(launch_copy_to_host(h_tail, counters.as<unsigned long long>() + 1, 8, st));
+                chk(launch_copy_to_host(h_items, counters.as<unsigned long long>(), 8, st));
+                chk(hipEventRecord(ev[4], st));
+                chk(hipStreamSynchronize(st));
+                idle = *h_items == before ? idle + 1 : 0;
+            }
+            for (size_t q = 0; q < err_seen.size(); ++q) hst[q].err |= err_seen[q];
+            ta.yield = nullptr;
+            if (yh && yh->finished) yh->finished();
         }
 
         bool overflow = false;
         float t_trav_extra = 0;
-        int32_t n_launches = budget_mode ? band_launches : 1;
+        int32_t n_launches = budget_mode ? band_launches : trav_launches;
         for (int32_t q = 0; q < nj; ++q) {
             if (hst[q].err & kErrDuplicate) jstat[ord[q]] = GSOFA_EINVAL;
             if (hst[q].err & kErrOverflow) overflow = true;
         }
         if (overflow) {
             // rows that did not fit: grow the pool, keep what fits, redo the rest
-            std::vector<int64_t> h_off(nrows);
-            std::vector<int32_t> h_cnt(nrows);
-            chk(hipMemcpyAsync(h_off.data(), row_off.p, 8 * nrows, hipMemcpyDeviceToHost, st));
-            chk(hipMemcpyAsync(h_cnt.data(), row_cnt.p, 4 * nrows, hipMemcpyDeviceToHost, st));
+            // per-row offsets and counts: through copy kernels and pinned memory
+            // when small, the runtime's copies into pageable memory otherwise
+            const size_t rows_b = 12 * (size_t)std::max<int64_t>(nrows, 1);
+            std::unique_ptr<PinnedBuf> h_rows;
+            std::vector<char> h_rows_big;
+            char* hr = nullptr;
+            if (rows_b <= kKernelCopyMax) {
+                h_rows = std::make_unique<PinnedBuf>(rows_b);
+                hr = h_rows->as<char>();
+                chk(launch_copy_to_host(hr, row_off.p, 8 * (size_t)nrows, st));
+                chk(launch_copy_to_host(hr + 8 * (size_t)nrows, row_cnt.p, 4 * (size_t)nrows, st));
+            } else {
+                h_rows_big.resize(rows_b);
+                hr = h_rows_big.data();
+                chk(hipMemcpyAsync(hr, row_off.p, 8 * (size_t)nrows, hipMemcpyDeviceToHost, st));
+                chk(hipMemcpyAsync(hr + 8 * (size_t)nrows, row_cnt.p, 4 * (size_t)nrows, hipMemcpyDeviceToHost, st));
+            }
             chk(hipStreamSynchronize(st));
+            const int64_t* h_off = reinterpret_cast<const int64_t*>(hr);
+            const int32_t* h_cnt = reinterpret_cast<const int32_t*>(hr + 8 * (size_t)nrows);
             std::vector<int32_t> redo;
             int64_t need = 0;
             for (int64_t r = 0; r < nrows; ++r)
@@ -1286,12 +1372,12 @@ struct Engine {
                 }
             const int64_t new_cap = pool_cap + need;
             DBuf pool2(4 * (size_t)new_cap);
-            chk(hipMemcpyAsync(pool2.p, pool.p, 4 * (size_t)pool_cap, hipMemcpyDeviceToDevice, st));
+            chk(launch_copy_device(pool2.p, pool.p, 4 * (size_t)pool_cap, st));
             pool = std::move(pool2);
             DBuf d_redo(4 * redo.size());
-            chk(hipMemcpyAsync(d_redo.p, redo.data(), 4 * redo.size(), hipMemcpyHostToDevice, st));
+            h2d(d_redo.p, redo.data(), 4 * redo.size(), st, false);
             unsigned long long cnt2[2] = {0ull, (unsigned long long)pool_cap};
-            chk(hipMemcpyAsync(counters.p, cnt2, 16, hipMemcpyHostToDevice, st));
+            h2d(counters.p, cnt2, 16, st, false);
             ta.item_rows = d_redo.as<int32_t>();
             ta.nitems = (int64_t)redo.size();
             ta.pool = pool.as<int32_t>();
@@ -1322,8 +1408,8 @@ struct Engine {
             }
             chk(hipEventRecord(ev[4], st));
             chk(launch_job_stats(d_jobs.as<Job>(), nj, N, row_stats.as<RowStat>(), jst.as<JobStats>(), st));
-            chk(hipMemcpyAsync(hst, jst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, st));
-            chk(hipMemcpyAsync(h_tail, counters.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, st));
+            chk(launch_copy_to_host(hst, jst.p, sizeof(JobStats) * nj, st));
+            chk(launch_copy_to_host(h_tail, counters.as<unsigned long long>() + 1, 8, st));
             chk(hipStreamSynchronize(st));
             for (int32_t q = 0; q < nj; ++q) {
                 if (hst[q].err & kErrOverflow) throw Status{GSOFA_ENOMEM};
@@ -1347,8 +1433,8 @@ struct Engine {
                                    scan_scr.as<int64_t>(), s));
             chk(launch_scan_counts(row_lcnt.as<int32_t>(), nullptr, nrows, l_rptr.as<int64_t>(),
                                    scan_scr.as<int64_t>(), s));
-            chk(hipMemcpyAsync(h_tot.as<int64_t>(), u_ptr.as<int64_t>() + nrows, 8, hipMemcpyDeviceToHost, s));
-            chk(hipMemcpyAsync(h_tot.as<int64_t>() + 1, l_rptr.as<int64_t>() + nrows, 8, hipMemcpyDeviceToHost, s));
+            chk(launch_copy_to_host(h_tot.as<int64_t>(), u_ptr.as<int64_t>() + nrows, 8, s));
+            chk(launch_copy_to_host(h_tot.as<int64_t>() + 1, l_rptr.as<int64_t>() + nrows, 8, s));
             ph.launch();
             chk(hipStreamSynchronize(st));
             ph.done();
@@ -1449,7 +1535,7 @@ struct Engine {
         Phase ph_sort(kPhaseSort, graphs, st);
         {
             const hipStream_t s = ph_sort.stream();
-            chk(hipMemcpyAsync(d_up.p, h_up.p, (size_t)up_bytes, hipMemcpyHostToDevice, s));
+            h2d(d_up.p, h_up.p, (size_t)up_bytes, s, true);
             if (nj > 1) chk(launch_row_job(d_ju, nj, N, row_job_user.as<int32_t>(), s));
             chk(launch_sort_rows(rs, row_off.as<int64_t>(), row_cnt.as<int32_t>(), row_lcnt.as<int32_t>(),
                                  pool.as<int32_t>(), u_ptr.as<int64_t>(), u_idx.as<int32_t>(),
@@ -1499,7 +1585,7 @@ struct Engine {
                 hipLaunchKernelGGL(k_gather_bounds, gb, dim3(256), 0, s, nj, d_jrb, nrows, start_scan.as<int64_t>(),
                                    d_b.as<int64_t>() + 2 * (nj + 1));
             chk(hipGetLastError());
-            chk(hipMemcpyAsync(h_b.p, d_b.p, 8 * 3 * (size_t)(nj + 1), hipMemcpyDeviceToHost, s));
+            chk(launch_copy_to_host(h_b.p, d_b.p, 8 * 3 * (size_t)(nj + 1), s));
             ph_col.launch();
         }
         chk(hipStreamSynchronize(st));
@@ -1545,15 +1631,39 @@ struct Engine {
             h_li = h_ui + nnz_u;
             h_xs = h_li + nnz_l;
             h_sn = h_xs + (have_sn ? nrows + nj : 0);
-            chk(hipMemcpyAsync(h_up_ptr, Up_loc, 8 * (size_t)nptr, hipMemcpyDeviceToHost, st));
-            chk(hipMemcpyAsync(h_lp_ptr, Lp_loc, 8 * (size_t)nptr, hipMemcpyDeviceToHost, st));
-            if (nnz_u) chk(hipMemcpyAsync(h_ui, u_idx.p, 4 * (size_t)nnz_u, hipMemcpyDeviceToHost, st));
-            if (nnz_l) chk(hipMemcpyAsync(h_li, Li, 4 * (size_t)nnz_l, hipMemcpyDeviceToHost, st));
+            // a small result comes back through copy kernels and one pinned block,
+            // a large one through the runtime's copies
+            struct Piece {
+                void* dst;
+                const void* src;
+                size_t bytes;
+            };
+            std::vector<Piece> pieces{{h_up_ptr, Up_loc, 8 * (size_t)nptr}, {h_lp_ptr, Lp_loc, 8 * (size_t)nptr},
+                                      {h_ui, u_idx.p, 4 * (size_t)nnz_u}, {h_li, Li, 4 * (size_t)nnz_l}};
             if (have_sn) {
-                chk(hipMemcpyAsync(h_xs, xsup_all.p, 4 * (size_t)(nrows + nj), hipMemcpyDeviceToHost, st));
-                chk(hipMemcpyAsync(h_sn, supno_all.p, 4 * (size_t)nrows, hipMemcpyDeviceToHost, st));
+                pieces.push_back({h_xs, xsup_all.p, 4 * (size_t)(nrows + nj)});
+                pieces.push_back({h_sn, supno_all.p, 4 * (size_t)nrows});
             }
-            chk(hipStreamSynchronize(st));
+            size_t small_b = 0;
+            for (auto& pc : pieces) small_b += pc.bytes;
+            if (small_b <= kKernelCopyMax) {
+                PinnedBuf out_stage(std::max<size_t>(small_b, 4));
+                size_t off = 0;
+                for (auto& pc : pieces) {
+                    chk(launch_copy_to_host(out_stage.as<char>() + off, pc.src, pc.bytes, st));
+                    off += pc.bytes;
+                }
+                chk(hipStreamSynchronize(st));
+                off = 0;
+                for (auto& pc : pieces) {
+                    if (pc.bytes) std::memcpy(pc.dst, out_stage.as<char>() + off, pc.bytes);
+                    off += pc.bytes;
+                }
+            } else {
+                for (auto& pc : pieces)
+                    if (pc.bytes) chk(hipMemcpyAsync(pc.dst, pc.src, pc.bytes, hipMemcpyDeviceToHost, st));
+                chk(hipStreamSynchronize(st));
+            }
         } else {
             keep = std::make_shared<std::vector<DBuf>>();
         }
@@ -1728,7 +1838,7 @@ struct Engine {
             chk(launch_traverse(ta, st));
             chk(hipEventRecord(ev[1], st));
             chk(launch_job_stats(d_jobs.as<Job>(), nj, N, t_rs.as<RowStat>(), tjst.as<JobStats>(), st));
-            chk(hipMemcpyAsync(h_js.p, tjst.p, sizeof(JobStats) * nj, hipMemcpyDeviceToHost, st));
+            chk(launch_copy_to_host(h_js.p, tjst.p, sizeof(JobStats) * nj, st));
             chk(hipStreamSynchronize(st));
             give_slots(std::move(ss));
             if (t < 0) continue;
@@ -1805,10 +1915,11 @@ int check_opts(const gsofa_opts* o) {
 std::mutex g_api_mu;  // one call at a time per process for the plain entry points
 
 int run_engine(std::vector<MatIn> mats, const gsofa_opts* o, std::vector<gsofa_result*>& outs,
-               bool allow_trials = true, bool tuned_with_slots = false) {
+               bool allow_trials = true, bool tuned_with_slots = false, const YieldHooks* yh = nullptr) {
     Engine eng;
     eng.mats = std::move(mats);
     eng.plan = make_plan(o);
+    eng.yh = yh;
     eng.plan.allow_trials = allow_trials && !(eng.plan.flags & GSOFA_NO_TUNE);
     eng.on_device = o && (o->flags & GSOFA_INPUT_ON_DEVICE);
     eng.st = o ? static_cast<hipStream_t>(o->stream) : nullptr;
@@ -2023,6 +2134,21 @@ struct gsofa_server {
     std::vector<std::thread> workers;
     int device = 0;
     int32_t slots_total = 5120;
+    // work-item admission: per worker, its yield flag (one 64-byte line of
+    // fine-grained pinned host memory each) and the state of its traversal
+    struct Worker {
+        uint32_t* flag = nullptr;
+        bool traversing = false;   // its traversal launches hold wave slots
+        bool yieldable = false;    // its current call polls the flag (a large request)
+        int32_t slots = 0;         // sources in flight of its current call
+        double last_yield_ms = -1e300;
+        uint64_t wait_for = 0;     // the admission it last yielded to
+    };
+    std::vector<Worker> wk;
+    void* flag_mem = nullptr;
+    uint64_t admit_seq = 0;
+    std::map<uint64_t, bool> admits_pending;  // admissions whose traversal is not enqueued yet
+    uint64_t yields = 0;                       // yield requests made (statistics)
 };
 
 namespace {
@@ -2032,14 +2158,23 @@ int64_t estimate_request_bytes(int32_t n, int64_t nnz, int32_t nslots) {
     return budget_for(n, nnz, nslots, lay);
 }
 
-// Sources in flight for one request: a share of the resident wavefronts (two
-// requests' kernels fill the device), never more than the request has rows,
-// and few enough that the request's estimate fits the whole budget; 0 if even
-// one source does not fit.
+// Wave slots no request's traversal takes by default: the row sorts, the L
+// transpose and the supernode kernels of a request admitted while large
+// traversals run find room there instead of waiting for their next yield.
+constexpr int32_t kServeReserveSlots = 256;
+
+// Sources in flight for one request: a share of the resident wavefronts less
+// the reserve (two requests' kernels fill the rest), never more than the
+// request has rows, and few enough that the request's estimate fits the whole
+// budget; 0 if even one source does not fit.
 int32_t serve_slots_for(const gsofa_server* s, int32_t n, int64_t nnz) {
     int32_t want;
-    if (s->opts.concurrent_sources > 0) want = std::min(s->opts.concurrent_sources, std::max(n, 1));
-    else want = std::min(std::max(s->slots_total / std::max(1, s->max_inflight / 2), 64), std::max(n, 1));
+    if (s->opts.concurrent_sources > 0) {
+        want = std::min(s->opts.concurrent_sources, std::max(n, 1));
+    } else {
+        const int32_t share = (s->slots_total - kServeReserveSlots) / std::max(1, s->max_inflight / 2) / 4 * 4;
+        want = std::min(std::max(share, 64), std::max(n, 1));
+    }
     const SlotLayout lay = slot_layout(std::max<int64_t>(n, 1));
     const int64_t rest = s->budget - budget_for(n, nnz, 0, lay);
     const int64_t fit = rest > 0 ? rest / (2 * lay.bytes_per_slot) : 0;
@@ -2059,6 +2194,18 @@ constexpr int64_t kServeGroupRows = 1 << 20;
 // and it is admitted as soon as its memory is free.
 constexpr int32_t kServeMaxPassed = 32;
 
+// Work-item admission (GSOFA_SERVE_YIELD): when a worker admits a request and
+// the traversals already running hold so many wave slots that its own would
+// find no room, it sets their yield flags. Each running launch then takes no further source,
+// finishes the ones it holds and ends; its engine relaunches from the work
+// counter once the new request's traversal is on its stream (or after
+// kServeResumeWaitMs), so the new request's wavefronts are dispatched first. A
+// traversal is asked at most once per kServeYieldGapMs, which bounds what a
+// stream of small requests costs a large one (a drain of about half a source
+// per slot each time).
+constexpr double kServeYieldGapMs = 20.0;
+constexpr int kServeResumeWaitMs = 20;
+
 long serve_pick(const gsofa_server* s) {
     if (s->queue.empty()) return -1;
     const auto fits = [&](const gsofa_server::Req& r) { return s->mem_in_use + r.est <= s->budget; };
@@ -2070,9 +2217,12 @@ long serve_pick(const gsofa_server* s) {
 
 void serve_worker(gsofa_server* s, int sid) {
     (void)hipSetDevice(s->device);
+    gsofa_server::Worker& me = s->wk[(size_t)sid];
     for (;;) {
         std::vector<gsofa_server::Req> grp;
         int64_t grp_est = 0;
+        int32_t want = 0;
+        uint64_t my_admit = 0;  // set if this admission asked running traversals to yield
         {
             std::unique_lock<std::mutex> lk(s->mu);
             long pick = -1;
@@ -2103,6 +2253,32 @@ void serve_worker(gsofa_server* s, int sid) {
             }
             s->inflight++;
             s->mem_in_use += grp_est;
+            int64_t rows = 0;
+            for (auto& r : grp) rows += r.n;
+            want = grp.size() == 1 ? grp[0].nslots : (int32_t)std::min<int64_t>(rows, s->slots_total);
+            int64_t busy = 0;
+            for (auto& w : s->wk)
+                if (w.traversing) busy += w.slots;
+            if ((s->opts.flags & GSOFA_SERVE_YIELD) && busy + want > s->slots_total - kServeReserveSlots) {
+                const double now = now_ms();
+                const uint64_t id = ++s->admit_seq;
+                for (auto& w : s->wk)
+                    if (w.traversing && w.yieldable && now - w.last_yield_ms >= kServeYieldGapMs) {
+                        __atomic_store_n(w.flag, 1u, __ATOMIC_RELEASE);
+                        w.last_yield_ms = now;
+                        w.wait_for = id;
+                        my_admit = id;
+                        s->yields++;
+                    }
+                if (my_admit) s->admits_pending[my_admit] = true;
+            }
+            s->wk[(size_t)sid].slots = want;
+            // only a lone large request polls the flag: its sources take
+            // milliseconds each, so one host-memory read per source costs
+            // nothing, while a group of small requests would poll millions of
+            // times a second (and finishes soon anyway)
+            s->wk[(size_t)sid].yieldable =
+                (s->opts.flags & GSOFA_SERVE_YIELD) && grp.size() == 1 && grp[0].n > kServeSmallRows;
         }
         gsofa_opts o = s->opts;
         o.stream = s->streams[sid];
@@ -2115,8 +2291,38 @@ void serve_worker(gsofa_server* s, int sid) {
         std::vector<gsofa_result*> outs;
         // no tuner trials inside a request (they would add to its latency), but
         // the size class's cached choice of mapping and window applies
-        const int rc = run_engine(std::move(mats), &o, outs, false, true);
+        YieldHooks hooks;
+        hooks.flag = me.yieldable ? me.flag : nullptr;
+        // a request set it after this worker's previous traversal had ended
+        __atomic_store_n(me.flag, 0u, __ATOMIC_RELEASE);
+        // the traversal is on the stream: it holds wave slots, and the
+        // traversals that yielded to this admission may resume
+        auto admitted_done = [&] {
+            if (my_admit) {
+                s->admits_pending.erase(my_admit);
+                my_admit = 0;
+                s->cv.notify_all();
+            }
+        };
+        hooks.enqueued = [&] {
+            std::lock_guard<std::mutex> g(s->mu);
+            me.traversing = true;
+            admitted_done();
+        };
+        hooks.finished = [&] {
+            std::lock_guard<std::mutex> g(s->mu);
+            me.traversing = false;
+        };
+        hooks.before_resume = [&] {
+            std::unique_lock<std::mutex> lk(s->mu);
+            const uint64_t id = me.wait_for;
+            s->cv.wait_for(lk, std::chrono::milliseconds(kServeResumeWaitMs),
+                           [&] { return s->closing || s->admits_pending.count(id) == 0; });
+        };
+        const int rc = run_engine(std::move(mats), &o, outs, false, true, &hooks);
         std::lock_guard<std::mutex> g(s->mu);
+        me.traversing = false;
+        admitted_done();
         for (size_t i = 0; i < grp.size(); ++i) {
             gsofa_result* res = i < outs.size() ? outs[i] : nullptr;
             int st = res ? res->stats.status : (rc != GSOFA_OK ? rc : GSOFA_EDEVICE);
@@ -2151,9 +2357,17 @@ extern "C" GSOFA_API int gsofa_serve_open(const gsofa_opts* opts, int32_t max_in
                                                  : (int64_t)((di.free_b + di.reclaimable) * 0.85);
         s->streams.assign(s->max_inflight, nullptr);
         for (auto& st : s->streams) chk(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        // yield flags: fine-grained (coherent) pinned memory, so that a running
+        // kernel sees the host's store
+        chk(hipHostMalloc(&s->flag_mem, 64 * (size_t)s->max_inflight, hipHostMallocCoherent));
+        std::memset(s->flag_mem, 0, 64 * (size_t)s->max_inflight);
+        s->wk.resize((size_t)s->max_inflight);
+        for (int i = 0; i < s->max_inflight; ++i)
+            s->wk[(size_t)i].flag = reinterpret_cast<uint32_t*>(static_cast<char*>(s->flag_mem) + 64 * i);
     } catch (...) {
         for (auto st : s->streams)
             if (st) (void)hipStreamDestroy(st);
+        if (s->flag_mem) (void)hipHostFree(s->flag_mem);
         delete s;
         return GSOFA_EDEVICE;
     }
@@ -2227,6 +2441,7 @@ extern "C" GSOFA_API int gsofa_serve_close(gsofa_server* s) {
         if (t.joinable()) t.join();
     for (auto& kv : s->done) free_result(kv.second.second);
     for (auto st : s->streams) (void)hipStreamDestroy(st);
+    if (s->flag_mem) (void)hipHostFree(s->flag_mem);
     delete s;
     return GSOFA_OK;
 }

@@ -93,6 +93,9 @@ struct TraverseArgs {
                                       // 4: as 0, compiled for seven wavefronts per SIMD;
                                       // 5: memory-budget kernel; 6: one thread per source (fill2)
     int32_t* host_spill;              // budget mode: pinned host memory, lay.h_stride entries per slot
+    const uint32_t* yield;            // optional flag in fine-grained host memory: when the host
+                                      // sets it, the launch stops taking work items (the ones taken
+                                      // are finished); item_counter then tells where to resume
 };
 
 // Row-space description shared by the assembly kernels. With one job,
@@ -107,6 +110,13 @@ hipError_t launch_validate(const Job* jobs_dev, int32_t njobs, int64_t max_n,
                            int32_t* bad_dev, hipStream_t st);
 hipError_t launch_init_slots(uint8_t* slots, int32_t nslots, SlotLayout lay, hipStream_t st);
 hipError_t launch_traverse(const TraverseArgs& a, hipStream_t st);
+// bytes (a multiple of 4) from device memory to pinned host memory, by a kernel
+// on the stream (no copy-engine packet that would wait behind earlier kernels)
+hipError_t launch_copy_to_host(void* dst, const void* src, size_t bytes, hipStream_t st);
+// bytes (a multiple of 4) from device memory to device memory, by a kernel
+hipError_t launch_copy_device(void* dst, const void* src, size_t bytes, hipStream_t st);
+// bytes (a multiple of 4) from pinned host memory to device memory, by a kernel
+hipError_t launch_copy_from_host(void* dst, const void* src, size_t bytes, hipStream_t st);
 // source slots that fit on the device at once (occupancy of the traversal kernel)
 int32_t traverse_resident_slots(int cus, int mapping);
 // out[base_j + i] = j for i < n_j, base = row_base (by_item false) or item_base

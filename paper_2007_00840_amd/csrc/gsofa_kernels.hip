@@ -103,6 +103,15 @@ __device__ __forceinline__ auto wg_xchg(T* p, U v) {
     return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// The host may ask a running launch to give its wave slots up (the request
+// server does so when a newly admitted request finds the device full): the flag
+// lives in fine-grained host memory and is read with system scope before each
+// work item is taken. A launch that sees it takes no further item; the items it
+// has taken are finished and the host relaunches from the work counter.
+__device__ __forceinline__ bool yield_requested(const TraverseArgs& a) {
+    return a.yield != nullptr && __hip_atomic_load(a.yield, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u;
+}
+
 // Order this wavefront's earlier global/LDS accesses before its later ones.
 __device__ __forceinline__ void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -375,7 +384,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
 
     for (;;) {
         unsigned long long k = 0;
-        if (ln == 0) k = atomicAdd(a.item_counter, 1ull);
+        if (ln == 0) k = yield_requested(a) ? ~0ull : atomicAdd(a.item_counter, 1ull);
         k = __shfl(k, 0, 64);
         if (k >= (unsigned long long)a.nitems) break;
 
@@ -870,7 +879,7 @@ __global__ __launch_bounds__(256) void k_traverse8(TraverseArgs a) {
 
     for (;;) {
         unsigned long long k = 0;
-        if (ln == 0) k = atomicAdd(a.item_counter, 1ull);
+        if (ln == 0) k = yield_requested(a) ? ~0ull : atomicAdd(a.item_counter, 1ull);
         k = __shfl(k, 0, 64);
         if (k >= (unsigned long long)a.nitems) break;
 
@@ -1301,7 +1310,7 @@ __global__ __launch_bounds__(64 * NW) void k_traverse_wg(TraverseArgs a) {
 
     for (;;) {
         if (tid == 0) {
-            const unsigned long long k = atomicAdd(a.item_counter, 1ull);
+            const unsigned long long k = yield_requested(a) ? ~0ull : atomicAdd(a.item_counter, 1ull);
             int32_t j = -1, s = 0;
             if (k < (unsigned long long)a.nitems) {
                 if (a.item_rows) {
@@ -1668,7 +1677,7 @@ __global__ __launch_bounds__(256) void k_fill2_thread(TraverseArgs a) {
     const int64_t N = a.lay.N;
 
     for (;;) {
-        const unsigned long long k = atomicAdd(a.item_counter, 1ull);
+        const unsigned long long k = yield_requested(a) ? ~0ull : atomicAdd(a.item_counter, 1ull);
         if (k >= (unsigned long long)a.nitems) break;
         int32_t j, s;
         if (a.item_rows) {
@@ -1897,6 +1906,61 @@ hipError_t launch_job_stats(const Job* jobs_dev, int32_t njobs, int64_t max_n, c
     if (njobs <= 0) return hipSuccess;
     const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_n + 4095) / 4096, 256));
     hipLaunchKernelGGL(k_job_stats, dim3(gx, njobs), dim3(256), 0, st, jobs_dev, njobs, row_stats, jstats);
+    return hipGetLastError();
+}
+
+// Small device-to-host transfers (statistics, counters, totals) as a kernel
+// that writes pinned host memory directly. A copy packet queued behind a
+// long-running kernel waits in a copy engine's queue, where it holds up the
+// copies of every other stream (a request's input upload waited for another
+// request's whole traversal); a kernel waits in its own stream only.
+__global__ void k_copy_to_host(const uint32_t* src, uint32_t* dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        __hip_atomic_store(&dst[i], src[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __threadfence_system();
+}
+
+// The other direction: pinned host memory (written by the host before the
+// launch) into device memory, read with system scope so that no cached copy of
+// an earlier use of the staging block is seen.
+__global__ void k_copy_from_host(const uint32_t* src, uint32_t* dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = __hip_atomic_load(&src[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_copy_from_host(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 4 != 0) return hipErrorInvalidValue;
+    const int64_t n = (int64_t)(bytes / 4);
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_copy_from_host, dim3(blocks), dim3(256), 0, st, static_cast<const uint32_t*>(src),
+                       static_cast<uint32_t*>(dst), n);
+    return hipGetLastError();
+}
+
+// Device-to-device copy (output-pool growth) in 256-thread workgroups.
+__global__ void k_copy_device(const uint32_t* src, uint32_t* dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy_device(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 4 != 0) return hipErrorInvalidValue;
+    const int64_t n = (int64_t)(bytes / 4);
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_copy_device, dim3(blocks), dim3(256), 0, st, static_cast<const uint32_t*>(src),
+                       static_cast<uint32_t*>(dst), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_to_host(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 4 != 0) return hipErrorInvalidValue;
+    const int64_t n = (int64_t)(bytes / 4);
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_copy_to_host, dim3(blocks), dim3(256), 0, st, static_cast<const uint32_t*>(src),
+                       static_cast<uint32_t*>(dst), n);
     return hipGetLastError();
 }
 

@@ -218,6 +218,39 @@ def test_graph_replays_match_eager(g):
     assert c1[1] > c0[1]
 
 
+def test_serve_work_item_admission(g):
+    """Two large requests with 4,096 sources in flight each fill the device;
+    with GSOFA_SERVE_YIELD small requests admitted while they traverse make
+    them yield (stop taking sources, let the small ones in, resume from the
+    work counter). Every result equals the oracle's with and without yielding;
+    with yielding at least one large traversal is relaunched, without it none
+    is (a pool-regrowth re-run at most)."""
+    big = [synth.stencil(27, (48, 48, 48), nd=True, seed=311 + k) for k in range(2)]
+    small = [synth.batch_member(500 + k) for k in range(40)]
+    refs_big = [oracle.symbolic(m.n, m.row_ptr, m.col_idx) for m in big]
+    refs_small = oracle_members(small)
+    launches = {}
+    for flags in (g.SERVE_YIELD, 0):
+        _say(f"work-item admission, flags {flags:#x}: 2 x n={big[0].n} + {len(small)} small")
+        with g.Server(max_inflight=4, concurrent_sources=4096, flags=flags) as srv:
+            tb = [srv.submit(m.n, m.row_ptr, m.col_idx) for m in big]
+            time.sleep(0.02)
+            ts = []
+            for m in small:
+                ts.append(srv.submit(m.n, m.row_ptr, m.col_idx))
+                time.sleep(0.01)
+            rb = [srv.poll(t, timeout_us=-1) for t in tb]
+            rs = [srv.poll(t, timeout_us=-1) for t in ts]
+        launches[flags] = [r.stats["launches"] for r in rb]
+        _say(f"large requests' traversal launches: {launches[flags]}")
+        for r, ref in zip(rb, refs_big):
+            assert same(r, ref)
+        for r, ref in zip(rs, refs_small):
+            assert same(r, ref)
+    assert sum(launches[g.SERVE_YIELD]) >= 3
+    assert max(launches[0]) <= 2
+
+
 def test_serve_groups_many_small_requests(g):
     """Many small requests queued at once share launches (a worker takes the
     queued small requests that fit its budget together); every result must
