@@ -770,13 +770,14 @@ int32_t auto_window(int64_t sources) {
 // Window span and traversal mapping change only the speed, never the result.
 // For a size class that has not been seen yet (device, log2 of the largest n,
 // mean row length, batch size) and a call with enough sources, the tuner times
-// every candidate on the same stratified sample of the call's sources
-// (kTuneSamplesPerSlot per slot), keeps the fastest, and reuses it for later
-// calls of the class.
-// Smaller calls use the defaults. The number of sources in flight is not tuned:
-// on a sample a few sources per slot long, fewer slots win by balancing the
-// tail better, while at full size they were twice as slow, so every candidate
-// runs on all resident wavefronts.
+// every candidate on a stratified sample of the call's sources
+// (kTuneScreenPerSlot per slot), times the kTuneFinalists fastest again on a
+// larger one (kTuneSamplesPerSlot per slot), keeps the fastest of those, and
+// reuses it for later calls of the class. Smaller calls use the defaults.
+// Sources in flight enter only as all resident wavefronts or half of them,
+// both with the same number of sources per slot: on a sample a few sources per
+// slot long, fewer slots win by balancing the tail better, while at full size
+// they were twice as slow.
 
 struct TuneKey {
     int cus, n_log2, deg_bucket, batch_log2;
@@ -806,7 +807,9 @@ constexpr TuneChoice kTuneCandidates[] = {
     {0, 4, 0, 1}, {0, 2, 0, 1}, {4, 4, 0, 1},
     {0, 16, GSOFA_NO_LINE95, 1}, {4, 8, GSOFA_NO_LINE95, 1}, {0, 16, 0, 2}, {4, 8, 0, 2},
 };
-constexpr int kTuneSamplesPerSlot = 24;
+constexpr int kTuneSamplesPerSlot = 24;  // final sample: sources per slot
+constexpr int kTuneScreenPerSlot = 8;    // first (screening) sample
+constexpr int kTuneFinalists = 3;        // candidates timed on the final sample
 
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneChoice>& tune_table() {
@@ -1762,25 +1765,43 @@ struct Engine {
                     int64_t budget, int64_t fixed, int64_t total_nnz, int64_t nrows, const DBuf& d_jobs,
                     PlanSlots plan_slots) {
         const int64_t R = plan_slots(0);
-        const int64_t S = std::min<int64_t>(items, std::max<int64_t>(R * kTuneSamplesPerSlot, 1));
-        // the sample, and every other entry of it for the candidates with half
-        // the sources in flight (the same number of sources per slot, so the
-        // tail weighs the same; candidates are compared by edges per second)
+        // Successive halving: every candidate on a first sample of
+        // kTuneScreenPerSlot sources per slot, the kTuneFinalists best of them
+        // on the full sample of kTuneSamplesPerSlot. Each sample is stratified
+        // over the call's sources; the candidates with half the sources in flight
+        // run every other entry of it (the same number of sources per slot, so
+        // the tail weighs the same; candidates are compared by edges per second).
+        const int64_t S = std::min<int64_t>(items - items / 64, std::max<int64_t>(R * kTuneSamplesPerSlot, 1));
         const int64_t S2 = std::max<int64_t>(S / 2, 1);
-        PinnedBuf h_s(4 * (size_t)(S + S2));
+        const int64_t T = std::min<int64_t>(items - items / 64, std::max<int64_t>(R * kTuneScreenPerSlot, 1));
+        const int64_t T2 = std::max<int64_t>(T / 2, 1);
+        PinnedBuf h_s(4 * (size_t)(S + S2 + T + T2));
         int32_t* smp = h_s.as<int32_t>();
-        int32_t q = 0;
-        for (int64_t i = 0; i < S; ++i) {
-            const int64_t k = (int64_t)((__int128)i * items / S);
-            while (q + 1 < nj && jt[q + 1].item_base <= k) ++q;
-            smp[i] = (int32_t)(jt[q].row_base + (jt[q].n - 1 - (k - jt[q].item_base)));
-        }
+        // The samples skip the first 1/64 of the work items (the highest source
+        // ids): in a nested-dissection order those are the top separators, whose
+        // sources reach most of the matrix. In a full launch they run first and
+        // overlap everything else, but in a trial a few sources per slot long
+        // they set the trial's length on their own (2D 9-point stencil: trials of
+        // ~200 ms where the sources' mean cost predicted ~20 ms).
+        const int64_t head = items / 64;
+        const int64_t span = std::max<int64_t>(items - head, 1);
+        auto stratified = [&](int32_t* out, int64_t count) {
+            int32_t q = 0;
+            for (int64_t i = 0; i < count; ++i) {
+                const int64_t k = head + (int64_t)((__int128)i * span / count);
+                while (q + 1 < nj && jt[q + 1].item_base <= k) ++q;
+                out[i] = (int32_t)(jt[q].row_base + (jt[q].n - 1 - (k - jt[q].item_base)));
+            }
+        };
+        stratified(smp, S);
         for (int64_t i = 0; i < S2; ++i) smp[S + i] = smp[std::min<int64_t>(2 * i, S - 1)];
-        DBuf d_s(4 * (size_t)(S + S2)), tcnt(64), tjst(sizeof(JobStats) * (size_t)std::max(nj, 1));
+        stratified(smp + S + S2, T);
+        for (int64_t i = 0; i < T2; ++i) smp[S + S2 + T + i] = smp[S + S2 + std::min<int64_t>(2 * i, T - 1)];
+        DBuf d_s(4 * (size_t)(S + S2 + T + T2)), tcnt(64), tjst(sizeof(JobStats) * (size_t)std::max(nj, 1));
         DBuf t_off(8 * (size_t)std::max<int64_t>(nrows, 1)), t_cnt(4 * (size_t)std::max<int64_t>(nrows, 1)),
             t_lcnt(4 * (size_t)std::max<int64_t>(nrows, 1)),
             t_rs(sizeof(RowStat) * (size_t)std::max<int64_t>(nrows, 1));
-        chk(hipMemcpyAsync(d_s.p, h_s.p, 4 * (size_t)(S + S2), hipMemcpyHostToDevice, st));
+        chk(launch_copy_from_host(d_s.p, h_s.p, 4 * (size_t)(S + S2 + T + T2), st));
         DBuf d_rj;
         if (nj > 1) {
             d_rj = DBuf(4 * (size_t)std::max<int64_t>(nrows, 1));
@@ -1798,23 +1819,17 @@ struct Engine {
         DBuf tpool(4 * (size_t)pcap);
         PinnedBuf h_js(sizeof(JobStats) * (size_t)std::max(nj, 1));
         EventSet ev;
-        TuneChoice best = kTuneCandidates[0];
-        double best_rate = 0;
-        bool have = false;
-        // The first candidate runs once untimed: the first launch on a new slot
-        // set also pays for touching its memory, which made that candidate lose
-        // by ~7 % to an equal one on the 64^3 27-point stencil.
-        constexpr int kCand = (int)(sizeof(kTuneCandidates) / sizeof(kTuneCandidates[0]));
-        for (int t = -1; t < kCand; ++t) {
-            const TuneChoice& c = kTuneCandidates[t < 0 ? 0 : t];
+        // one trial: edges per millisecond of candidate c on the full or the
+        // first sample
+        auto trial = [&](const TuneChoice& c, bool full) -> double {
             const int64_t ns = div_slots(plan_slots(c.mapping), c.div);
             auto ss = take_slots(lay, (int32_t)ns, c.mapping == 3 ? 1 : 0, st);
             TraverseArgs ta{};
             ta.jobs = d_jobs.as<Job>();
             ta.njobs = nj;
             ta.nslots = (int32_t)std::min<int64_t>(ns, ss->nslots);
-            ta.nitems = c.div == 2 ? S2 : S;
-            ta.item_rows = d_s.as<int32_t>() + (c.div == 2 ? S : 0);
+            ta.nitems = full ? (c.div == 2 ? S2 : S) : (c.div == 2 ? T2 : T);
+            ta.item_rows = d_s.as<int32_t>() + (full ? (c.div == 2 ? S : 0) : (c.div == 2 ? S + S2 + T : S + S2));
             ta.row_job = d_rj.as<int32_t>();
             ta.item_job = nullptr;
             ta.row_stats = t_rs.as<RowStat>();
@@ -1841,14 +1856,31 @@ struct Engine {
             chk(launch_copy_to_host(h_js.p, tjst.p, sizeof(JobStats) * nj, st));
             chk(hipStreamSynchronize(st));
             give_slots(std::move(ss));
-            if (t < 0) continue;
             float ms = 0;
             chk(hipEventElapsedTime(&ms, ev[0], ev[1]));
             double edges = 0;
             for (int32_t jj = 0; jj < nj; ++jj) edges += (double)h_js.as<JobStats>()[jj].edges_alg;
-            const double rate = edges / std::max(1e-3, (double)ms);
+            return edges / std::max(1e-3, (double)ms);
+        };
+        constexpr int kCand = (int)(sizeof(kTuneCandidates) / sizeof(kTuneCandidates[0]));
+        // The first candidate runs once untimed: the first launch on a new slot
+        // set also pays for touching its memory, which made that candidate lose
+        // by ~7 % to an equal one on the 64^3 27-point stencil.
+        (void)trial(kTuneCandidates[0], false);
+        std::vector<std::pair<double, int>> screen;
+        for (int t = 0; t < kCand; ++t) screen.push_back({trial(kTuneCandidates[t], false), t});
+        std::stable_sort(screen.begin(), screen.end(),
+                         [](const std::pair<double, int>& x, const std::pair<double, int>& y) { return x.first > y.first; });
+        std::vector<int> fin;
+        for (int i = 0; i < kCand && i < kTuneFinalists; ++i) fin.push_back(screen[(size_t)i].second);
+        std::sort(fin.begin(), fin.end());  // candidate order is the prior
+        TuneChoice best = kTuneCandidates[fin[0]];
+        double best_rate = 0;
+        bool have = false;
+        for (int t : fin) {
+            const double rate = trial(kTuneCandidates[t], true);
             if (!have || rate > best_rate * 1.05) {
-                best = c;
+                best = kTuneCandidates[t];
                 best_rate = rate;
                 have = true;
             }
