@@ -265,10 +265,12 @@ GSOFA_API int gsofa_batch(int32_t count, const gsofa_csr* mats, const gsofa_opts
                 gsofa_result** outs);
 
 /*
- * Request server with continuous batching: requests are admitted in arrival
- * order while their estimated device memory fits the budget
- * (opts->mem_budget_bytes, default: free device memory plus what the library
- * holds idle) and fewer than max_inflight workers are busy; a worker that
+ * Request server with continuous batching: a free worker (at most
+ * max_inflight are busy) admits the oldest queued request whose estimated
+ * device memory fits what is left of the budget (opts->mem_budget_bytes,
+ * default: free device memory plus what the library holds idle); a request
+ * waiting for memory is passed by later ones at most 32 times, then admitted
+ * before any other once its memory is free. A worker that
  * admits a request of at most 65,536 rows also takes the later queued small
  * requests that fit (up to 64 and 2^20 rows together) and runs them as one
  * persistent launch, as gsofa_batch does. Admitted work runs concurrently on

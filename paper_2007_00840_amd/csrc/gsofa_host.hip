@@ -2135,11 +2135,11 @@ extern "C" GSOFA_API int gsofa_graph_counters(uint64_t* out) {
 // ------------------------------------------------------------ the server
 //
 // Continuous batching: max_inflight worker threads, each with its own stream,
-// take requests from the arrival queue in order whenever the head request's
-// memory estimate fits what is left of the budget. Requests that arrive while
-// others run are admitted as soon as a worker and memory are free, and their
-// kernels overlap on the device with the running ones. A finished request
-// returns its memory to the budget and wakes the waiting workers.
+// take the oldest queued request whose memory estimate fits what is left of the
+// budget (serve_pick), together with later small ones that fit. Requests that
+// arrive while others run are admitted as soon as a worker and memory are free,
+// and their kernels overlap on the device with the running ones. A finished
+// request returns its memory to the budget and wakes the waiting workers.
 
 struct gsofa_server {
     gsofa_opts opts{};
