@@ -428,9 +428,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         }
         ++epoch;
         const uint32_t base = 0xFFFFFFFFu - epoch * R;
-        auto dec = [&](uint32_t v) -> uint32_t {
-            return (v >= base && v - base < R) ? v - base : kInf;
-        };
+        // This source's labels lie in [base, base + R); every older word lies at
+        // or above base + R (earlier ranges sit higher, the initial word is the
+        // top value). So the relaxation compares encoded words directly:
+        // "not reached" is w >= baseR, "value x lowers it" is base + x < w, and
+        // "already in the structure" is w < base + v.
+        const uint32_t baseR = base + R;
 
         // a source's first-visit degrees sum to at most nnz < 2^31: 32 bits per lane
         uint32_t e_alg = 0;
@@ -456,7 +459,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
                     fresh = (wg_or(&ub[w >> 5], bit) & bit) == 0u;
                 } else {
                     const uint32_t old = wg_min(&lab[w], base);  // label 0: no intermediate vertex
-                    fresh = dec(old) != 0u;
+                    fresh = old != base;  // base is label 0: seeded already (a repeated column)
                 }
                 dup |= !fresh;
             }
@@ -553,15 +556,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
                     const int32_t fs = rp[f];
                     const int32_t deg = act ? rp[f + 1] - fs : 0;
                     if (fr < 0) e_alg += (uint32_t)deg;
-                    const uint32_t dl = dec(ld_coherent(&lab[f]));
-                    const uint32_t ov = (dl == kInf) ? kInf : max(dl, (uint32_t)f);
+                    // encoded value this row passes on: max(label, f), or the top
+                    // word (lowers nothing) if the row holds no label
+                    const uint32_t lf = ld_coherent(&lab[f]);
+                    const uint32_t ov = lf >= baseR ? kInf : max(lf, base + (uint32_t)f);
                     const int32_t incl = wave_incl_scan(deg);
                     const int32_t total = uni(__shfl(incl, 63, 64));
                     e_gpu += (unsigned long long)total;
                     // one round: kIlp independent edges per lane; every load of the
                     // round is issued before any of its results is used
                     // own[k]: lane holding the row of edge k. A lane's row passes on
-                    // ov, or with refresh set the value decoded from fraw (its label
+                    // ov, or with refresh set the value taken from fraw (its label
                     // re-read); both are taken once the round's loads are in flight.
                     auto round = [&](int32_t (&widx)[kIlp], int32_t (&own)[kIlp], uint32_t fraw, bool refresh,
                                      bool (&act_e)[kIlp]) {
@@ -590,15 +595,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
                             }
                         }
                         {
-                            const uint32_t dr = dec(fraw);
-                            const uint32_t ovr = refresh ? ((dr == kInf) ? kInf : max(dr, (uint32_t)f)) : ov;
+                            const uint32_t ovr = refresh ? (fraw >= baseR ? kInf : max(fraw, base + (uint32_t)f)) : ov;
 #pragma unroll
                             for (int kk = 0; kk < kIlp; ++kk) outv[kk] = (uint32_t)__shfl((int)ovr, own[kk], 64);
                         }
                         auto keyof = [&](int kk) -> unsigned long long {
                             uint32_t wv = (uint32_t)w[kk];
                             asm volatile("" : "+v"(wv));
-                            return ((unsigned long long)(wv >> kDedupBits) << 39) |
+                            return ((unsigned long long)(wv >> kDedupBits) << 40) |
                                    ((unsigned long long)(wv > (uint32_t)s ? 0u : outv[kk]) << 8) |
                                    (unsigned long long)(kk * 64 + ln);
                         };
@@ -606,10 +610,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
                         bool cand[kIlp];
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
-                            const uint32_t d = dec(lv[kk]);
                             if (B && w[kk] > s) cand[kk] = act_e[kk] && (lv[kk] & (1u << (w[kk] & 31))) == 0u;
-                            else if (w[kk] > s) cand[kk] = act_e[kk] && d == kInf;
-                            else cand[kk] = act_e[kk] && outv[kk] < d && !(line95 && d < (uint32_t)w[kk]);
+                            else if (w[kk] > s) cand[kk] = act_e[kk] && lv[kk] >= baseR;
+                            else cand[kk] = act_e[kk] && outv[kk] < lv[kk] && !(line95 && lv[kk] < base + (uint32_t)w[kk]);
                         }
                         // Candidates of one round that share a target all saw the label
                         // as it was before the round; only the one with the smallest value
@@ -640,7 +643,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
                             for (int kk = 0; kk < kIlp; ++kk) {
                                 if (cand[kk]) {
                                     const unsigned long long r = RT[slot(kk)], kq = keyof(kk);
-                                    cand[kk] = r == kq || (r >> 39) != (kq >> 39);
+                                    cand[kk] = r == kq || (r >> 40) != (kq >> 40);
                                 }
                             }
                         }
@@ -653,23 +656,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
                                                           ? base : kInf)
                                                    : base;
                             else
-                                old[kk] = cand[kk] ? wg_min(&lab[w[kk]], base + (w[kk] > s ? 0u : outv[kk])) : base;
+                                old[kk] = cand[kk] ? wg_min(&lab[w[kk]], w[kk] > s ? base : outv[kk]) : base;
                         }
                         bool emit[kIlp], isl[kIlp], push[kIlp], first[kIlp];
 #pragma unroll
                         for (int kk = 0; kk < kIlp; ++kk) {
                             const int32_t wk = w[kk];
                             const uint32_t ov = outv[kk];
-                            const uint32_t dold = dec(old[kk]);
+                            const uint32_t ow = old[kk];
+                            const uint32_t bw = base + (uint32_t)wk;
                             emit[kk] = isl[kk] = push[kk] = false;
-                            first[kk] = cand[kk] && wk < s && dold == kInf;
+                            first[kk] = cand[kk] && wk < s && ow >= baseR;
                             if (!cand[kk]) continue;
                             if (wk > s) {
-                                emit[kk] = dold == kInf;
+                                emit[kk] = ow >= baseR;
                                 continue;
                             }
-                            if (ov < dold && dold >= (uint32_t)wk) {
-                                if (ov < (uint32_t)wk) {
+                            if (ov < ow && ow >= bw) {
+                                if (ov < bw) {
                                     // label fell below w: fill (s, w)
                                     emit[kk] = true;
                                     isl[kk] = true;
