@@ -1771,21 +1771,22 @@ struct Engine {
         // over the call's sources; the candidates with half the sources in flight
         // run every other entry of it (the same number of sources per slot, so
         // the tail weighs the same; candidates are compared by edges per second).
-        const int64_t S = std::min<int64_t>(items - items / 64, std::max<int64_t>(R * kTuneSamplesPerSlot, 1));
+        const int64_t S = std::min<int64_t>(items, std::max<int64_t>(R * kTuneSamplesPerSlot, 1));
         const int64_t S2 = std::max<int64_t>(S / 2, 1);
         const int64_t T = std::min<int64_t>(items - items / 64, std::max<int64_t>(R * kTuneScreenPerSlot, 1));
         const int64_t T2 = std::max<int64_t>(T / 2, 1);
         PinnedBuf h_s(4 * (size_t)(S + S2 + T + T2));
         int32_t* smp = h_s.as<int32_t>();
-        // The samples skip the first 1/64 of the work items (the highest source
-        // ids): in a nested-dissection order those are the top separators, whose
-        // sources reach most of the matrix. In a full launch they run first and
-        // overlap everything else, but in a trial a few sources per slot long
-        // they set the trial's length on their own (2D 9-point stencil: trials of
-        // ~200 ms where the sources' mean cost predicted ~20 ms).
-        const int64_t head = items / 64;
-        const int64_t span = std::max<int64_t>(items - head, 1);
-        auto stratified = [&](int32_t* out, int64_t count) {
+        // The screening sample skips the first 1/64 of the work items (the
+        // highest source ids): in a nested-dissection order those are the top
+        // separators, whose sources reach most of the matrix. In a full launch
+        // they run first and overlap everything else, but in a short trial they
+        // set its length on their own (2D 9-point stencil: trials of ~200 ms
+        // where the sources' mean cost predicted ~20 ms). The final sample keeps
+        // them: without them a near-tie on the 64^3 27-point stencil went to a
+        // candidate 5 % slower at full size.
+        auto stratified = [&](int32_t* out, int64_t count, int64_t head) {
+            const int64_t span = std::max<int64_t>(items - head, 1);
             int32_t q = 0;
             for (int64_t i = 0; i < count; ++i) {
                 const int64_t k = head + (int64_t)((__int128)i * span / count);
@@ -1793,9 +1794,9 @@ struct Engine {
                 out[i] = (int32_t)(jt[q].row_base + (jt[q].n - 1 - (k - jt[q].item_base)));
             }
         };
-        stratified(smp, S);
+        stratified(smp, S, 0);
         for (int64_t i = 0; i < S2; ++i) smp[S + i] = smp[std::min<int64_t>(2 * i, S - 1)];
-        stratified(smp + S + S2, T);
+        stratified(smp + S + S2, T, items / 64);
         for (int64_t i = 0; i < T2; ++i) smp[S + S2 + T + i] = smp[S + S2 + std::min<int64_t>(2 * i, T - 1)];
         DBuf d_s(4 * (size_t)(S + S2 + T + T2)), tcnt(64), tjst(sizeof(JobStats) * (size_t)std::max(nj, 1));
         DBuf t_off(8 * (size_t)std::max<int64_t>(nrows, 1)), t_cnt(4 * (size_t)std::max<int64_t>(nrows, 1)),
@@ -1871,8 +1872,14 @@ struct Engine {
         for (int t = 0; t < kCand; ++t) screen.push_back({trial(kTuneCandidates[t], false), t});
         std::stable_sort(screen.begin(), screen.end(),
                          [](const std::pair<double, int>& x, const std::pair<double, int>& y) { return x.first > y.first; });
-        std::vector<int> fin;
-        for (int i = 0; i < kCand && i < kTuneFinalists; ++i) fin.push_back(screen[(size_t)i].second);
+        // finalists: the first candidate (the prior's choice, replaced only by a
+        // finalist 5 % faster on the final sample) and the kTuneFinalists best
+        // of the screening. Short screening trials are noisy near ties: without
+        // the first candidate in the final, the 64^3 27-point stencil went to
+        // one 5 % slower at full size in four tunings out of five.
+        std::vector<int> fin{0};
+        for (int i = 0; i < kCand && (int)fin.size() <= kTuneFinalists; ++i)
+            if (screen[(size_t)i].second != 0) fin.push_back(screen[(size_t)i].second);
         std::sort(fin.begin(), fin.end());  // candidate order is the prior
         TuneChoice best = kTuneCandidates[fin[0]];
         double best_rate = 0;
