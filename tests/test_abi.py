@@ -138,6 +138,16 @@ def test_order_above_limit_rejected(g):
     assert lib.gsofa_symbolic_noalloc(g.MAX_N + 1, rp.ctypes.data, ci.ctypes.data, None,
                                       u_ptr.ctypes.data, None, 0, l_ptr.ctypes.data, None, 0,
                                       xs.ctypes.data, xs.ctypes.data, ctypes.byref(c)) == g.EINVAL
+    # a batch whose every member is refused runs nothing and reports each one
+    for flags in (0, g.INPUT_ON_DEVICE):
+        mats = (g.Csr * 2)(g.Csr(g.MAX_N + 1, rp.ctypes.data, ci.ctypes.data),
+                           g.Csr(-1, rp.ctypes.data, ci.ctypes.data))
+        outs = (ctypes.POINTER(g.Result) * 2)()
+        o = g.make_opts(flags=flags)
+        assert lib.gsofa_batch(2, mats, ctypes.byref(o), outs) == g.EINVAL
+        for r in outs:
+            assert r and r.contents.stats.status == g.EINVAL
+            lib.gsofa_result_free(r)
 
 
 def test_batch_argument_errors(g):

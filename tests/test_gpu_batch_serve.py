@@ -167,6 +167,10 @@ def test_serve_status_codes(g):
         with pytest.raises(g.GsofaError) as e:
             srv.submit(m.n, m.row_ptr, bad)
         assert e.value.code == g.EINVAL
+        # an order above GSOFA_MAX_N is refused before its arrays are read
+        with pytest.raises(g.GsofaError) as e:
+            srv.submit(g.MAX_N + 1, m.row_ptr[:2], m.col_idx[:1])
+        assert e.value.code == g.EINVAL
     with g.Server(max_inflight=1, mem_budget_bytes=1 << 20) as srv:
         with pytest.raises(g.GsofaError) as e:
             srv.submit(m.n, m.row_ptr, m.col_idx)
