@@ -265,19 +265,36 @@ class DeviceResult:
         r = rp.contents
         self.n, self.nnz_l, self.nnz_u, self.nsuper = r.n, r.nnz_l, r.nnz_u, r.nsuper
         self.fills = r.fills
-        self.stats = _stats(r)
-        self.ptrs = {k: getattr(r, k) for k in ("l_ptr", "l_idx", "u_ptr", "u_idx", "xsup", "supno")}
+        # the statistics are copied as they are and turned into a dict on first
+        # use (a batch returns thousands of results); they outlive free()
+        self._st = Stats.from_buffer_copy(r.stats)
+        self._stats = None
+
+    @property
+    def stats(self) -> dict:
+        if self._stats is None:
+            self._stats = {f: getattr(self._st, f) for f, _ in Stats._fields_}
+        return self._stats
+
+    @property
+    def ptrs(self) -> dict:
+        """Device addresses of the result arrays (valid until free())."""
+        if self._rp is None:
+            raise ValueError("result already freed")
+        r = self._rp.contents
+        return {k: getattr(r, k) for k in ("l_ptr", "l_idx", "u_ptr", "u_idx", "xsup", "supno")}
 
     def to_torch(self, device="cuda"):
         """Copy the device arrays into torch tensors (device to device)."""
         import torch
         out = {}
+        ptrs = self.ptrs
         sizes = {"l_ptr": (self.n + 1, torch.int64), "u_ptr": (self.n + 1, torch.int64),
                  "l_idx": (self.nnz_l, torch.int32), "u_idx": (self.nnz_u, torch.int32),
                  "xsup": (self.nsuper + 1, torch.int32), "supno": (self.n, torch.int32)}
         for k, (cnt, dt) in sizes.items():
             t = torch.empty(max(cnt, 0), dtype=dt, device=device)
-            p = self.ptrs[k]
+            p = ptrs[k]
             if cnt > 0 and p:
                 _d2d(t.data_ptr(), p, t.numel() * t.element_size())
             out[k] = t
@@ -306,16 +323,29 @@ def _d2d(dst, src, nbytes):
         raise GsofaError(EDEVICE, "hipMemcpy")
 
 
+_torch = None
+
+
+def _torch_mod():
+    global _torch
+    if _torch is None:
+        try:
+            import torch
+            _torch = torch
+        except ImportError:  # pragma: no cover
+            _torch = False
+    return _torch
+
+
 def _arr_ptr(a):
     """(pointer, keepalive, on_device) of a numpy array or a torch tensor."""
-    try:
-        import torch
-        if isinstance(a, torch.Tensor):
-            if a.dtype != torch.int32 or not a.is_contiguous():
-                raise TypeError("CSR tensors must be contiguous int32")
-            return a.data_ptr(), a, a.is_cuda
-    except ImportError:  # pragma: no cover
-        pass
+    if isinstance(a, np.ndarray) and a.dtype == np.int32 and a.flags.c_contiguous:
+        return a.ctypes.data, a, False
+    torch = _torch_mod()
+    if torch and isinstance(a, torch.Tensor):
+        if a.dtype != torch.int32 or not a.is_contiguous():
+            raise TypeError("CSR tensors must be contiguous int32")
+        return a.data_ptr(), a, a.is_cuda
     arr = np.ascontiguousarray(a, dtype=np.int32)
     return arr.ctypes.data, arr, False
 
