@@ -910,9 +910,11 @@ __global__ void k_rebase_ptr(int32_t njobs, const int64_t* job_row_base, const i
 // `before_resume` returns (the admitted request's traversal is enqueued by
 // then, or a bounded wait has passed). `enqueued` runs once the first traversal
 // launch of the call is on the stream, `finished` once the traversal is done.
+// `before_traverse` runs before the traversal is enqueued (the call's uploads
+// and sorts are on the stream by then) and may wait.
 struct YieldHooks {
     uint32_t* flag = nullptr;
-    std::function<void()> enqueued, finished, before_resume;
+    std::function<void()> enqueued, finished, before_resume, before_traverse;
 };
 
 struct Engine {
@@ -1267,6 +1269,7 @@ struct Engine {
             return (int32_t)(r - *(it - 1));
         };
 
+        if (yh && yh->before_traverse) yh->before_traverse();
         chk(hipEventRecord(ev[0], st));
         if (budget_mode) {
             if (nj > 1) chk(launch_row_job(d_jobs.as<Job>(), nj, N, d_row_job.as<int32_t>(), st));
@@ -2180,6 +2183,8 @@ struct gsofa_server {
         bool traversing = false;   // its traversal launches hold wave slots
         bool yieldable = false;    // its current call polls the flag (a large request)
         int32_t slots = 0;         // sources in flight of its current call
+        bool alone = false;        // its call was given the idle device's wave slots
+        bool alone_trav = false;   // ... and its traversal has not ended yet
         double last_yield_ms = -1e300;
         uint64_t wait_for = 0;     // the admission it last yielded to
     };
@@ -2216,6 +2221,19 @@ int32_t serve_slots_for(const gsofa_server* s, int32_t n, int64_t nnz) {
     }
     const SlotLayout lay = slot_layout(std::max<int64_t>(n, 1));
     const int64_t rest = s->budget - budget_for(n, nnz, 0, lay);
+    const int64_t fit = rest > 0 ? rest / (2 * lay.bytes_per_slot) : 0;
+    return (int32_t)std::min<int64_t>(want, fit);
+}
+
+// Sources in flight for a request admitted onto an idle server (nothing running,
+// nothing queued): every resident wavefront but the reserve, within the budget.
+// The share above assumes two large requests at once; a lone one would leave
+// half the device idle (the largest request of a 1-per-second stream took
+// 141 ms against 110 ms as a plain call).
+int32_t serve_slots_alone(const gsofa_server* s, int32_t n, int64_t nnz) {
+    const int32_t want = std::min((s->slots_total - kServeReserveSlots) / 4 * 4, std::max(n, 1));
+    const SlotLayout lay = slot_layout(std::max<int64_t>(n, 1));
+    const int64_t rest = s->budget - s->mem_in_use - budget_for(n, nnz, 0, lay);
     const int64_t fit = rest > 0 ? rest / (2 * lay.bytes_per_slot) : 0;
     return (int32_t)std::min<int64_t>(want, fit);
 }
@@ -2290,6 +2308,15 @@ void serve_worker(gsofa_server* s, int sid) {
                     }
                 }
             }
+            if (grp.size() == 1 && s->inflight == 0 && s->queue.empty() && s->opts.concurrent_sources <= 0) {
+                const int32_t slots = serve_slots_alone(s, grp[0].n, (int64_t)grp[0].ci.size());
+                if (slots > grp[0].nslots) {
+                    me.alone = me.alone_trav = true;
+                    grp[0].nslots = slots;
+                    grp[0].est = estimate_request_bytes(grp[0].n, (int64_t)grp[0].ci.size(), slots);
+                    grp_est = grp[0].est;
+                }
+            }
             s->inflight++;
             s->mem_in_use += grp_est;
             int64_t rows = 0;
@@ -2351,7 +2378,24 @@ void serve_worker(gsofa_server* s, int sid) {
         hooks.finished = [&] {
             std::lock_guard<std::mutex> g(s->mu);
             me.traversing = false;
+            if (me.alone_trav) {
+                me.alone_trav = false;
+                s->cv.notify_all();
+            }
         };
+        // A large request admitted while one that was given the idle device
+        // traverses uploads and sorts at once but starts its traversal when that
+        // traversal ends: its wavefronts could only queue behind it, and would
+        // take the reserve the small requests need as they got room.
+        if (!me.alone && grp.size() == 1 && grp[0].n > kServeSmallRows)
+            hooks.before_traverse = [&] {
+                std::unique_lock<std::mutex> lk(s->mu);
+                s->cv.wait(lk, [&] {
+                    for (auto& w : s->wk)
+                        if (w.alone_trav) return false;
+                    return true;
+                });
+            };
         hooks.before_resume = [&] {
             std::unique_lock<std::mutex> lk(s->mu);
             const uint64_t id = me.wait_for;
@@ -2372,6 +2416,7 @@ void serve_worker(gsofa_server* s, int sid) {
             s->done[grp[i].ticket] = {st, res};
         }
         s->inflight--;
+        me.alone = me.alone_trav = false;
         s->mem_in_use -= grp_est;
         s->cv.notify_all();
     }
