@@ -212,7 +212,8 @@ def make_opts(flags=0, max_supernode=0, mem_budget_bytes=0, window=0,
 
 @dataclass
 class SymbolicResult:
-    """Host copy of a gsofa_result (all arrays numpy)."""
+    """A host gsofa_result: its arrays are numpy views of the library's result
+    memory (page-locked where available), released when the last view is gone."""
     n: int
     nnz_a: int
     nnz_l: int
@@ -229,12 +230,30 @@ class SymbolicResult:
     stats: dict
 
 
-def _np_from(ptr, count, dtype):
+class _Hold:
+    """Owns a library host result while numpy arrays view its memory (a copy of
+    a 64^3 stencil's 1.6 GB of indices would hold the interpreter for 0.1 s)."""
+
+    __slots__ = ("_rp", "_free")
+
+    def __init__(self, rp, free):
+        self._rp = rp
+        self._free = free
+
+    def __del__(self):
+        try:
+            self._free(self._rp)
+        except Exception:
+            pass
+
+
+def _np_view(ptr, count, dtype, hold):
     if count <= 0 or not ptr:
         return np.zeros(max(count, 0), dtype=dtype)
     ct = np.ctypeslib.as_ctypes_type(np.dtype(dtype))
     buf = (ct * count).from_address(ptr)
-    return np.frombuffer(buf, dtype=dtype).copy()
+    buf._hold = hold  # the array's base keeps the result alive
+    return np.frombuffer(buf, dtype=dtype)
 
 
 def _stats(r: Result) -> dict:
@@ -242,17 +261,19 @@ def _stats(r: Result) -> dict:
     return {f: getattr(s, f) for f, _ in Stats._fields_}
 
 
-def _to_host(rp) -> SymbolicResult:
+def _to_host(rp, lib) -> SymbolicResult:
+    """Takes ownership of the library result rp (freed with the last array)."""
+    hold = _Hold(rp, lib.gsofa_result_free)
     r = rp.contents
     n = r.n
     has_sn = bool(r.xsup)
     return SymbolicResult(
         n=n, nnz_a=r.nnz_a, nnz_l=r.nnz_l, nnz_u=r.nnz_u, fills=r.fills,
-        l_ptr=_np_from(r.l_ptr, n + 1, np.int64), l_idx=_np_from(r.l_idx, r.nnz_l, np.int32),
-        u_ptr=_np_from(r.u_ptr, n + 1, np.int64), u_idx=_np_from(r.u_idx, r.nnz_u, np.int32),
+        l_ptr=_np_view(r.l_ptr, n + 1, np.int64, hold), l_idx=_np_view(r.l_idx, r.nnz_l, np.int32, hold),
+        u_ptr=_np_view(r.u_ptr, n + 1, np.int64, hold), u_idx=_np_view(r.u_idx, r.nnz_u, np.int32, hold),
         nsuper=r.nsuper,
-        xsup=_np_from(r.xsup, r.nsuper + 1, np.int32) if has_sn else None,
-        supno=_np_from(r.supno, n, np.int32) if has_sn else None,
+        xsup=_np_view(r.xsup, r.nsuper + 1, np.int32, hold) if has_sn else None,
+        supno=_np_view(r.supno, n, np.int32, hold) if has_sn else None,
         flags=r.flags, stats=_stats(r))
 
 
@@ -371,10 +392,7 @@ def symbolic(n, row_ptr, col_idx, flags=0, max_supernode=0, mem_budget_bytes=0, 
         raise GsofaError(rc, "gsofa_symbolic")
     if flags & RESULT_ON_DEVICE:
         return DeviceResult(out)
-    try:
-        return _to_host(out)
-    finally:
-        lib.gsofa_result_free(out)
+    return _to_host(out, lib)
 
 
 def batch(mats, flags=0, max_supernode=0, mem_budget_bytes=0, window=0,
@@ -421,8 +439,7 @@ def batch(mats, flags=0, max_supernode=0, mem_budget_bytes=0, window=0,
         elif flags & RESULT_ON_DEVICE:
             results.append(DeviceResult(p))
         else:
-            results.append(_to_host(p))
-            lib.gsofa_result_free(p)
+            results.append(_to_host(p, lib))
     if rc != OK and raise_on_error:
         for r in results:
             if isinstance(r, DeviceResult):
@@ -505,10 +522,7 @@ class Server:
             return None
         if rc != OK:
             raise GsofaError(rc, "gsofa_serve_poll")
-        try:
-            return _to_host(out)
-        finally:
-            self._lib.gsofa_result_free(out)
+        return _to_host(out, self._lib)
 
     def close(self):
         if self._h:

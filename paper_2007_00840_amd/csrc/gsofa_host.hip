@@ -377,6 +377,76 @@ SpillCache& spill_cache() {
     return *c;
 }
 
+// Host memory for results. A result lands in page-locked memory: the device's
+// copy engine writes it at the link's rate while every compute unit is busy
+// (800 MB in 15 ms), where fresh pageable memory takes 200 ms (each page faults
+// in during the copy, and the runtime stages it through kernels). Freeing
+// page-locked memory waits for all work on the device, so released blocks are
+// kept for later results (best fit within twice the size), up to
+// kResultIdleMax bytes; only beyond that does a release free, and wait. Where
+// no page-locked memory is left, a block comes from malloc.
+constexpr size_t kResultIdleMax = 8ull << 30;
+
+class ResultBlocks {
+   public:
+    struct Block {
+        void* p = nullptr;
+        bool pinned = false;
+    };
+    Block take(size_t bytes) {
+        bytes = (bytes + 65535) & ~size_t(65535);
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            auto it = idle_.lower_bound(bytes);
+            if (it != idle_.end() && it->first <= bytes * 2 + (1u << 20)) {
+                void* p = it->second;
+                size_[p] = it->first;
+                pooled_ -= it->first;
+                idle_.erase(it);
+                return {p, true};
+            }
+        }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, bytes, hipHostMallocDefault) == hipSuccess && p) {
+            std::lock_guard<std::mutex> g(mu_);
+            size_[p] = bytes;
+            return {p, true};
+        }
+        (void)hipGetLastError();
+        return {std::malloc(bytes), false};
+    }
+    // p came from take() as page-locked; the call that filled it has synchronised
+    void give(void* p) {
+        std::vector<void*> drop;
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            auto it = size_.find(p);
+            if (it == size_.end()) return;
+            idle_.emplace(it->second, p);
+            pooled_ += it->second;
+            size_.erase(it);
+            while (pooled_ > kResultIdleMax) {
+                auto big = std::prev(idle_.end());
+                pooled_ -= big->first;
+                drop.push_back(big->second);
+                idle_.erase(big);
+            }
+        }
+        for (void* q : drop) (void)hipHostFree(q);
+    }
+
+   private:
+    std::mutex mu_;
+    std::multimap<size_t, void*> idle_;
+    std::unordered_map<void*, size_t> size_;
+    size_t pooled_ = 0;
+};
+
+ResultBlocks& result_blocks() {
+    static ResultBlocks* r = new ResultBlocks();  // lives until process end
+    return *r;
+}
+
 struct PinnedBuf {
     void* p = nullptr;
     explicit PinnedBuf(size_t b) : p(pinned_pool().take(std::max<size_t>(b, 8))) {}
@@ -1628,17 +1698,33 @@ struct Engine {
         if (!dev_out) {
             const size_t bytes = 8 * 2 * (size_t)nptr + 4 * (size_t)(nnz_u + nnz_l) +
                                  (have_sn ? 4 * (size_t)(nrows + nj + nrows) : 0) + 64;
-            void* blk = std::malloc(bytes);
+            const ResultBlocks::Block rb = result_blocks().take(bytes);
+            void* blk = rb.p;
             if (!blk) throw Status{GSOFA_ENOMEM};
-            hblock = std::shared_ptr<void>(blk, [](void* q) { std::free(q); });
+            // until the copies into it have completed, an error returns the block
+            // only after the stream has drained
+            struct Guard {
+                ResultBlocks::Block b;
+                hipStream_t st;
+                bool armed = true;
+                ~Guard() {
+                    if (!armed) return;
+                    (void)hipStreamSynchronize(st);
+                    (void)hipGetLastError();
+                    if (b.pinned) result_blocks().give(b.p);
+                    else std::free(b.p);
+                }
+            } guard{rb, st};
             h_up_ptr = static_cast<int64_t*>(blk);
             h_lp_ptr = h_up_ptr + nptr;
             h_ui = reinterpret_cast<int32_t*>(h_lp_ptr + nptr);
             h_li = h_ui + nnz_u;
             h_xs = h_li + nnz_l;
             h_sn = h_xs + (have_sn ? nrows + nj : 0);
-            // a small result comes back through copy kernels and one pinned block,
-            // a large one through the runtime's copies
+            // into page-locked memory a small result comes back through copy
+            // kernels, a large one through the copy engine; into pageable memory
+            // a small one through copy kernels and a pinned block, a large one
+            // through the runtime's staged copies
             struct Piece {
                 void* dst;
                 const void* src;
@@ -1652,7 +1738,16 @@ struct Engine {
             }
             size_t small_b = 0;
             for (auto& pc : pieces) small_b += pc.bytes;
-            if (small_b <= kKernelCopyMax) {
+            if (rb.pinned) {
+                for (auto& pc : pieces) {
+                    if (!pc.bytes) continue;
+                    if (small_b <= kKernelCopyMax)
+                        chk(launch_copy_to_host(pc.dst, pc.src, pc.bytes, st));
+                    else
+                        chk(hipMemcpyAsync(pc.dst, pc.src, pc.bytes, hipMemcpyDeviceToHost, st));
+                }
+                chk(hipStreamSynchronize(st));
+            } else if (small_b <= kKernelCopyMax) {
                 PinnedBuf out_stage(std::max<size_t>(small_b, 4));
                 size_t off = 0;
                 for (auto& pc : pieces) {
@@ -1670,6 +1765,11 @@ struct Engine {
                     if (pc.bytes) chk(hipMemcpyAsync(pc.dst, pc.src, pc.bytes, hipMemcpyDeviceToHost, st));
                 chk(hipStreamSynchronize(st));
             }
+            guard.armed = false;
+            if (rb.pinned)
+                hblock = std::shared_ptr<void>(blk, [](void* q) { result_blocks().give(q); });
+            else
+                hblock = std::shared_ptr<void>(blk, [](void* q) { std::free(q); });
         } else {
             keep = std::make_shared<std::vector<DBuf>>();
         }

@@ -327,3 +327,36 @@ def test_autotuner_trials_keep_results(g):
     assert again.stats["t_tune_ms"] == 0
     assert (again.stats["mapping"], again.stats["window"]) == (res.stats["mapping"], res.stats["window"])
     assert_same(again, ref)
+
+
+def test_host_results_outlive_their_result_object(g):
+    """Host result arrays view the library's result memory: they stay valid after
+    the result object is gone and later calls have taken and returned result
+    memory, and a result large enough for the copy-engine download (above
+    8 MiB) equals the device-resident result of the same call."""
+    import gc
+    m = synth.stencil(27, (30, 30, 30), nd=True, seed=81)
+    other = synth.stencil(27, (30, 30, 29), nd=True, seed=82)
+    _say(f"host result views n={m.n}")
+    a = g.symbolic(m.n, m.row_ptr, m.col_idx, flags=g.NO_TUNE)
+    assert 4 * (a.nnz_l + a.nnz_u) > (8 << 20)
+    d = g.symbolic(m.n, m.row_ptr, m.col_idx, flags=g.NO_TUNE | g.RESULT_ON_DEVICE)
+    t = d.to_torch()
+    d.free()
+    for k in ("l_ptr", "l_idx", "u_ptr", "u_idx", "xsup", "supno"):
+        assert np.array_equal(getattr(a, k), t[k].cpu().numpy()), k
+    keep = {k: getattr(a, k) for k in ("l_idx", "u_idx", "supno")}
+    want = {k: v.copy() for k, v in keep.items()}
+    del a
+    gc.collect()
+    for _ in range(2):
+        b = g.symbolic(other.n, other.row_ptr, other.col_idx, flags=g.NO_TUNE)
+        del b
+        gc.collect()
+    for k in keep:
+        assert np.array_equal(keep[k], want[k]), k
+    del keep
+    gc.collect()
+    c = g.symbolic(m.n, m.row_ptr, m.col_idx, flags=g.NO_TUNE)
+    for k in want:
+        assert np.array_equal(getattr(c, k), want[k]), k
