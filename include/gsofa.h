@@ -31,6 +31,10 @@
  *   - inputs are caller-owned and read-only; nothing is retained after a call
  *     returns (serve_submit copies its input).
  *   - results are library-owned; release them with gsofa_result_free.
+ *     Host result arrays are in page-locked memory where the system has it
+ *     (pageable memory otherwise); released blocks are kept for later results
+ *     up to 8 GiB, and a release beyond that frees memory, which waits for
+ *     the work running on the device.
  *   - no C++ exception crosses this boundary; every entry point returns a
  *     gsofa_status and leaves its output arguments untouched on error.
  *   - one library instance drives the current HIP device of the calling
@@ -276,7 +280,10 @@ GSOFA_API int gsofa_batch(int32_t count, const gsofa_csr* mats, const gsofa_opts
  * persistent launch, as gsofa_batch does. Admitted work runs concurrently on
  * the device and finished requests release their memory, which admits the
  * next. A request's traversal takes a share of the resident wavefronts less
- * a reserve of 256 that kernels of requests admitted meanwhile run in; with
+ * a reserve of 256 that kernels of requests admitted meanwhile run in; a
+ * request admitted with nothing else running or queued takes every resident
+ * wavefront but the reserve, and a large request (over 65,536 rows) admitted
+ * while its traversal runs starts its own traversal when that one ends; with
  * GSOFA_SERVE_YIELD running large traversals also give their wave slots up to
  * a request admitted onto a full device. Requests never time tuner trials
  * (cached choices or defaults).
