@@ -213,7 +213,9 @@ def make_opts(flags=0, max_supernode=0, mem_budget_bytes=0, window=0,
 @dataclass
 class SymbolicResult:
     """A host gsofa_result: its arrays are numpy views of the library's result
-    memory (page-locked where available), released when the last view is gone."""
+    memory (page-locked where available), released when the last view is gone.
+    The results of one batch call share one block, released with the last of
+    them."""
     n: int
     nnz_a: int
     nnz_l: int

@@ -222,6 +222,47 @@ def test_graph_replays_match_eager(g):
     assert c1[1] > c0[1]
 
 
+_LARGE = []
+
+
+def _two_large():
+    """Two 48^3 27-point stencils (110,592 rows: large requests) and their oracle
+    results, computed once for the tests that use them."""
+    if not _LARGE:
+        big = [synth.stencil(27, (48, 48, 48), nd=True, seed=311 + k) for k in range(2)]
+        _LARGE.append((big, [oracle.symbolic(m.n, m.row_ptr, m.col_idx) for m in big]))
+    return _LARGE[0]
+
+
+def test_serve_lone_request_takes_the_device(g):
+    """A request admitted onto an idle server runs with every resident
+    wavefront but the reserve; a large request admitted while it traverses gets
+    the ordinary share and starts its traversal when the first one's ends.
+    Both results, and those of small requests admitted meanwhile, equal the
+    oracle's."""
+    big, refs_big = _two_large()
+    small = [synth.batch_member(700 + k) for k in range(10)]
+    refs_small = oracle_members(small)
+    _say(f"lone request then another: 2 x n={big[0].n} + {len(small)} small")
+    with g.Server(max_inflight=4) as srv:
+        ta = srv.submit(big[0].n, big[0].row_ptr, big[0].col_idx)
+        time.sleep(0.02)
+        tb = srv.submit(big[1].n, big[1].row_ptr, big[1].col_idx)
+        ts = []
+        for m in small:
+            ts.append(srv.submit(m.n, m.row_ptr, m.col_idx))
+            time.sleep(0.005)
+        ra = srv.poll(ta, timeout_us=-1)
+        rb = srv.poll(tb, timeout_us=-1)
+        rs = [srv.poll(t, timeout_us=-1) for t in ts]
+    ca, cb = ra.stats["concurrent_sources"], rb.stats["concurrent_sources"]
+    _say(f"sources in flight: lone {ca}, admitted meanwhile {cb}")
+    assert ca > cb and ca <= big[0].n
+    assert same(ra, refs_big[0]) and same(rb, refs_big[1])
+    for r, ref in zip(rs, refs_small):
+        assert same(r, ref)
+
+
 def test_serve_work_item_admission(g):
     """Two large requests with 4,096 sources in flight each fill the device;
     with GSOFA_SERVE_YIELD small requests admitted while they traverse make
@@ -229,9 +270,8 @@ def test_serve_work_item_admission(g):
     work counter). Every result equals the oracle's with and without yielding;
     with yielding at least one large traversal is relaunched, without it none
     is (a pool-regrowth re-run at most)."""
-    big = [synth.stencil(27, (48, 48, 48), nd=True, seed=311 + k) for k in range(2)]
+    big, refs_big = _two_large()
     small = [synth.batch_member(500 + k) for k in range(40)]
-    refs_big = [oracle.symbolic(m.n, m.row_ptr, m.col_idx) for m in big]
     refs_small = oracle_members(small)
     launches = {}
     for flags in (g.SERVE_YIELD, 0):
