@@ -2423,9 +2423,12 @@ void serve_worker(gsofa_server* s, int sid) {
             for (auto& r : grp) rows += r.n;
             want = grp.size() == 1 ? grp[0].nslots : (int32_t)std::min<int64_t>(rows, s->slots_total);
             int64_t busy = 0;
-            for (auto& w : s->wk)
+            bool gated = false;  // waits for a lone request's traversal (below): nothing to yield to
+            for (auto& w : s->wk) {
                 if (w.traversing) busy += w.slots;
-            if ((s->opts.flags & GSOFA_SERVE_YIELD) && busy + want > s->slots_total - kServeReserveSlots) {
+                if (w.alone_trav && !me.alone && grp.size() == 1 && grp[0].n > kServeSmallRows) gated = true;
+            }
+            if ((s->opts.flags & GSOFA_SERVE_YIELD) && !gated && busy + want > s->slots_total - kServeReserveSlots) {
                 const double now = now_ms();
                 const uint64_t id = ++s->admit_seq;
                 for (auto& w : s->wk)
