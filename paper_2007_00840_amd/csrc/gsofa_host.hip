@@ -1069,10 +1069,11 @@ struct Engine {
             }
             in_rp = DBuf(4 * (size_t)std::max<int64_t>(rp_tot, 1));
             in_ci = DBuf(4 * (size_t)std::max<int64_t>(ci_tot, 1));
-            // pack through a pinned staging buffer
+            // pack through a pinned staging buffer, kept to the end of the call
+            // (its copies complete by the traversal's synchronisation)
             const size_t stage_b = 4 * (size_t)(rp_tot + ci_tot);
-            PinnedBuf stage(std::max<size_t>(stage_b, 4));
-            int32_t* sp = stage.as<int32_t>();
+            staged.push_back(std::make_unique<PinnedBuf>(std::max<size_t>(stage_b, 4)));
+            int32_t* sp = staged.back()->as<int32_t>();
             for (int32_t j = 0; j < nj; ++j) {
                 if (mats[j].n > 0) {
                     std::memcpy(sp + rp_off[j], mats[j].rp, 4 * (size_t)(mats[j].n + 1));
@@ -1083,7 +1084,6 @@ struct Engine {
             }
             h2d(in_rp.p, sp, 4 * (size_t)rp_tot, st, true);
             h2d(in_ci.p, sp + rp_tot, 4 * (size_t)ci_tot, st, true);
-            chk(hipStreamSynchronize(st));
             for (int32_t j = 0; j < nj; ++j) {
                 jobs[j].row_ptr = in_rp.as<int32_t>() + rp_off[j];
                 jobs[j].col_idx = in_ci.as<int32_t>() + ci_off[j];
