@@ -31,10 +31,11 @@
  *   - inputs are caller-owned and read-only; nothing is retained after a call
  *     returns (serve_submit copies its input).
  *   - results are library-owned; release them with gsofa_result_free.
- *     Host result arrays are in page-locked memory where the system has it
- *     (pageable memory otherwise); released blocks are kept for later results
- *     up to 8 GiB, and a release beyond that frees memory, which waits for
- *     the work running on the device.
+ *     Host result arrays of 1 MiB or more together are in page-locked memory
+ *     where the system has it (pageable memory otherwise, and for smaller
+ *     results); released blocks are kept for later results up to 8 GiB, and a
+ *     release beyond that frees memory, which waits for the work running on
+ *     the device.
  *   - no C++ exception crosses this boundary; every entry point returns a
  *     gsofa_status and leaves its output arguments untouched on error.
  *   - one library instance drives the current HIP device of the calling

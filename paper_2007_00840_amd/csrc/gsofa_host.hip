@@ -384,8 +384,11 @@ SpillCache& spill_cache() {
 // page-locked memory waits for all work on the device, so released blocks are
 // kept for later results (best fit within twice the size), up to
 // kResultIdleMax bytes; only beyond that does a release free, and wait. Where
-// no page-locked memory is left, a block comes from malloc.
+// no page-locked memory is left, a block comes from malloc, and so does a
+// result below kResultPinnedMin bytes (many small results kept by a caller
+// would otherwise lock memory by the 64 KiB block).
 constexpr size_t kResultIdleMax = 8ull << 30;
+constexpr size_t kResultPinnedMin = 1u << 20;
 
 class ResultBlocks {
    public:
@@ -394,6 +397,7 @@ class ResultBlocks {
         bool pinned = false;
     };
     Block take(size_t bytes) {
+        if (bytes < kResultPinnedMin) return {std::malloc(bytes), false};
         bytes = (bytes + 65535) & ~size_t(65535);
         {
             std::lock_guard<std::mutex> g(mu_);
