@@ -99,8 +99,9 @@ typedef enum {
  * (traversal; pointer scans; row sort; supernodes; L transpose and result
  * pointers) is captured into HIP graphs and each phase is one graph launch;
  * executable graphs are cached per phase and updated in place for the next
- * call. GSOFA_EAGER launches every kernel on the stream instead; results are
- * identical. */
+ * call. GSOFA_EAGER launches every kernel on the stream instead, and so does
+ * a call on one matrix of at most 65,536 rows, whose phases are too short for
+ * capture to pay; results are identical. */
 #define GSOFA_EAGER             0x200u
 /* With window = 0, concurrent_sources = 0 and no mapping or ablation flag, the
  * window span, the mapping and the sources in flight are autotuned: for each
