@@ -204,3 +204,49 @@ def test_bench_reads_its_traffic_record():
         if window + 1 not in windows:
             assert bench.recorded_traffic(kernel, mapping, window + 1, sources) is None
         assert bench.recorded_traffic(kernel, mapping, window, sources + 4) is None
+
+
+def test_host_result_views_keep_the_result_alive(g):
+    """Host result arrays are numpy views of the library's memory; the library
+    result is freed once, when the last of them is gone (binding logic only:
+    a result assembled in host memory and a counting stand-in for
+    gsofa_result_free)."""
+    import gc
+
+    n, nnz_l, nnz_u, nsuper = 5, 7, 6, 3
+    arrs = {"l_ptr": np.arange(n + 1, dtype=np.int64), "u_ptr": np.arange(n + 1, dtype=np.int64) * 2,
+            "l_idx": np.arange(nnz_l, dtype=np.int32) + 10, "u_idx": np.arange(nnz_u, dtype=np.int32) + 20,
+            "xsup": np.array([0, 2, 4, 5], dtype=np.int32), "supno": np.array([0, 0, 1, 1, 2], dtype=np.int32)}
+    res = g.Result()
+    res.n, res.nnz_l, res.nnz_u, res.nsuper = n, nnz_l, nnz_u, nsuper
+    for k, a in arrs.items():
+        setattr(res, k, a.ctypes.data)
+    rp = ctypes.pointer(res)
+    freed = []
+
+    class Lib:
+        @staticmethod
+        def gsofa_result_free(p):
+            freed.append(ctypes.addressof(p.contents))
+
+    r = g._to_host(rp, Lib)
+    for k, a in arrs.items():
+        v = getattr(r, k)
+        assert np.array_equal(v, a) and v.ctypes.data == a.ctypes.data, k
+    del v
+    keep = r.u_idx
+    del r
+    gc.collect()
+    assert freed == []
+    assert np.array_equal(keep, arrs["u_idx"])
+    del keep
+    gc.collect()
+    assert freed == [ctypes.addressof(res)]
+
+    # an empty result: zero-length arrays, freed with the result object
+    empty = g.Result()
+    r = g._to_host(ctypes.pointer(empty), Lib)
+    assert r.l_idx.size == 0 and r.u_ptr.size == 1 and r.xsup is None
+    del r
+    gc.collect()
+    assert len(freed) == 2
