@@ -377,10 +377,10 @@ SpillCache& spill_cache() {
     return *c;
 }
 
-// Host memory for results. A result lands in page-locked memory: the device's
-// copy engine writes it at the link's rate while every compute unit is busy
-// (800 MB in 15 ms), where fresh pageable memory takes 200 ms (each page faults
-// in during the copy, and the runtime stages it through kernels). Freeing
+// Host memory for results. A result lands in page-locked memory, written by
+// the library's copy kernel at the link's rate (690 MB in 13 ms), where fresh
+// pageable memory takes 200 ms per 800 MB (each page faults in during the
+// copy, and the runtime stages it through its own kernels). Freeing
 // page-locked memory waits for all work on the device, so released blocks are
 // kept for later results (best fit within twice the size), up to
 // kResultIdleMax bytes; only beyond that does a release free, and wait. Where
@@ -1732,10 +1732,12 @@ struct Engine {
             h_li = h_ui + nnz_u;
             h_xs = h_li + nnz_l;
             h_sn = h_xs + (have_sn ? nrows + nj : 0);
-            // into page-locked memory a small result comes back through copy
-            // kernels, a large one through the copy engine; into pageable memory
-            // a small one through copy kernels and a pinned block, a large one
-            // through the runtime's staged copies
+            // into page-locked memory every result comes back through the copy
+            // kernel (as fast as the runtime's copy, which dispatched 512- and
+            // 1,024-thread workgroups that wait for room next to running
+            // traversals); into pageable memory a small one through the copy
+            // kernel and a pinned block, a large one through the runtime's
+            // staged copies
             struct Piece {
                 void* dst;
                 const void* src;
@@ -1750,13 +1752,8 @@ struct Engine {
             size_t small_b = 0;
             for (auto& pc : pieces) small_b += pc.bytes;
             if (rb.pinned) {
-                for (auto& pc : pieces) {
-                    if (!pc.bytes) continue;
-                    if (small_b <= kKernelCopyMax)
-                        chk(launch_copy_to_host(pc.dst, pc.src, pc.bytes, st));
-                    else
-                        chk(hipMemcpyAsync(pc.dst, pc.src, pc.bytes, hipMemcpyDeviceToHost, st));
-                }
+                for (auto& pc : pieces)
+                    if (pc.bytes) chk(launch_copy_to_host(pc.dst, pc.src, pc.bytes, st));
                 chk(hipStreamSynchronize(st));
             } else if (small_b <= kKernelCopyMax) {
                 PinnedBuf out_stage(std::max<size_t>(small_b, 4));

@@ -332,8 +332,8 @@ def test_autotuner_trials_keep_results(g):
 def test_host_results_outlive_their_result_object(g):
     """Host result arrays view the library's result memory: they stay valid after
     the result object is gone and later calls have taken and returned result
-    memory, and a result large enough for the copy-engine download (above
-    8 MiB) equals the device-resident result of the same call."""
+    memory, and a result in a page-locked block (above 1 MiB) equals the
+    device-resident result of the same call."""
     import gc
     m = synth.stencil(27, (30, 30, 30), nd=True, seed=81)
     other = synth.stencil(27, (30, 30, 29), nd=True, seed=82)
