@@ -761,8 +761,7 @@ int check_csr_host(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<
 // ------------------------------------------------------------------ results
 
 struct ResultOwner {
-    // host arrays (malloc) or device buffers shared by the results of one call
-    std::vector<void*> host;
+    // the host block or the device buffers shared by the results of one call
     std::shared_ptr<void> shared_host;
     std::shared_ptr<std::vector<DBuf>> dev;
 };
@@ -772,14 +771,6 @@ gsofa_result* new_result() {
     if (!r) throw Status{GSOFA_ENOMEM};
     r->internal_ = new ResultOwner();
     return r;
-}
-
-template <typename T>
-T* host_array(gsofa_result* r, int64_t count) {
-    void* p = std::malloc(sizeof(T) * (size_t)std::max<int64_t>(count, 1));
-    if (!p) throw Status{GSOFA_ENOMEM};
-    static_cast<ResultOwner*>(r->internal_)->host.push_back(p);
-    return static_cast<T*>(p);
 }
 
 // ------------------------------------------------------------ the pipeline
@@ -2023,10 +2014,7 @@ struct Engine {
 void free_result(gsofa_result* r) {
     if (!r) return;
     auto* own = static_cast<ResultOwner*>(r->internal_);
-    if (own) {
-        for (void* p : own->host) std::free(p);
-        delete own;
-    }
+    delete own;
     std::free(r);
 }
 
