@@ -468,8 +468,9 @@ struct PinnedBuf {
 // device memory with kernels of 512- and 1,024-thread workgroups, which wait
 // for a compute unit with that much room, and there is none while persistent
 // traversals of other calls hold the device: a 2,000-row server request's
-// input upload waited 0.4 s behind two 64^3 traversals. Larger transfers keep
-// the runtime's copies.
+// input upload waited 0.4 s behind two 64^3 traversals. Larger uploads go
+// from pinned staging by hipMemcpyAsync, which runs on the copy engine; results
+// of any size come back through the copy kernel into page-locked blocks.
 constexpr size_t kKernelCopyMax = 8u << 20;
 
 // ------------------------------------------------------------ HIP graphs
