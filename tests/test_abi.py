@@ -250,3 +250,15 @@ def test_host_result_views_keep_the_result_alive(g):
     del r
     gc.collect()
     assert len(freed) == 2
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU per process: --gpus above 1 exits with a
+    message (before touching a GPU)."""
+    import json
+    import sys
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    msg = json.loads(p.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
